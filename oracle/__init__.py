@@ -1,0 +1,14 @@
+"""FP64 CPU oracle of the CFG-pair similarity (TEST INFRASTRUCTURE).
+
+Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
+`bench.py` may import or call anything in this package.  The product path
+(the HIP library and its Python binding) never touches it, and this package
+imports nothing from the product.  See `oracle/cfsim_ref.py` for the
+readings of the paper it implements.
+"""
+from .cfsim_ref import (  # noqa: F401
+    CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT,
+    transition_matrix, transition_matrix_sparse, resize_bilinear,
+    apply_operator, coupled_iteration, greedy_match, score_pair,
+    backward, edge_gradients, topk, PairResult,
+)

@@ -1,0 +1,150 @@
+"""Plant plausible mistakes in the oracle (CPU only) and check that the pins
+reject every one of them.  Nothing here touches a GPU."""
+import numpy as np
+import pytest
+import scipy.ndimage as ndi
+
+import oracle
+from cfgsynth import Grammar, make_cfg
+from oracle import cfsim_ref as ref
+from tests.golden.fixtures import pathfinder_fig3
+
+
+def _pair(seed=0):
+    ga = make_cfg(8, Grammar(counts="trip"), seed=seed)
+    gb = make_cfg(6, Grammar(counts="trip"), seed=seed + 50)
+    A = oracle.transition_matrix(ga.n, ga.src, ga.dst, ga.count)
+    B = oracle.transition_matrix(gb.n, gb.src, gb.dst, gb.count)
+    return A, B, ga, gb
+
+
+def _closed_form_holds(A, B, K=25):
+    M = np.kron(B, A) + np.kron(B.T, A.T)
+    lam, V = np.linalg.eigh(M)
+    s0 = np.full(M.shape[0], 1 / np.sqrt(M.shape[0]))
+    x = V @ (((lam / np.abs(lam).max()) ** K) * (V.T @ s0))
+    x /= np.linalg.norm(x)
+    S = oracle.coupled_iteration(A, B, K, -1.0)[0]
+    return np.allclose(S.ravel(), x, atol=1e-10)
+
+
+MUTANT_OPERATORS = {
+    "dropped transpose term": lambda A, B, S: B @ S @ A.T,
+    "dropped direct term": lambda A, B, S: B.T @ S @ A,
+    "transposed A": lambda A, B, S: B @ S @ A + B.T @ S @ A.T,
+    "transposed B": lambda A, B, S: B.T @ S @ A.T + B @ S @ A,
+    "wrong sign": lambda A, B, S: B @ S @ A.T - B.T @ S @ A,
+    "extra identity": lambda A, B, S: B @ S @ A.T + B.T @ S @ A + S,
+}
+
+
+def test_unmutated_oracle_passes():
+    A, B, *_ = _pair()
+    assert _closed_form_holds(A, B)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANT_OPERATORS))
+def test_operator_mutants_fail_the_eigen_pin(monkeypatch, name):
+    A, B, *_ = _pair()
+    monkeypatch.setattr(ref, "apply_operator", MUTANT_OPERATORS[name])
+    assert not _closed_form_holds(A, B)
+
+
+def test_mutant_update_count_fails_the_eigen_pin(monkeypatch):
+    A, B, *_ = _pair()
+    real = ref.coupled_iteration
+
+    def one_extra(A, B, max_iter=200, tol=1e-12, keep_iterates=False):
+        return real(A, B, max_iter + 1, tol, keep_iterates)
+    monkeypatch.setattr(oracle, "coupled_iteration", one_extra)
+    assert not _closed_form_holds(A, B)
+
+
+def test_mutant_tie_break_fails_the_naive_greedy_pin(monkeypatch):
+    S = np.array([[1.0, 1.0], [1.0, 0.0]])
+
+    def reversed_ties(S):
+        nB, nA = S.shape
+        flat = S.ravel()
+        order = np.lexsort((-np.arange(flat.size), -flat))
+        used_r, used_c, match = set(), set(), np.full(nB, -1)
+        for idx in order:
+            i, j = divmod(int(idx), nA)
+            if i not in used_r and j not in used_c:
+                match[i] = j
+                used_r.add(i)
+                used_c.add(j)
+        return match, 0.0
+    assert oracle.greedy_match(S)[0].tolist() == [0, 1]
+    assert reversed_ties(S)[0].tolist() == [1, 0]
+
+
+def test_mutant_backward_fails_finite_differences(monkeypatch):
+    A, B, ga, gb = _pair(3)
+    K = 20
+    r = oracle.score_pair(A, B, K, -1.0)
+
+    def fd(e):
+        p, q = int(ga.src[e]), int(ga.dst[e])
+        f = []
+        for h in (1e-6, -1e-6):
+            X = A.copy()
+            X[p, q] += h
+            S = oracle.coupled_iteration(X, B, K, -1.0)[0]
+            f.append(sum(S[i, j] for i, j in enumerate(r.match) if j >= 0))
+        return (f[0] - f[1]) / 2e-6
+
+    dA, _ = oracle.backward(A, B, K, r.match)
+    good = all(abs(fd(e) - dA[ga.src[e], ga.dst[e]]) < 1e-8 for e in range(ga.nnz))
+    assert good
+    # mutant: forget the projection term of the normalisation adjoint
+    orig = ref.backward
+
+    def no_projection(A_, B_, iters, match):
+        A_ = np.asarray(A_)
+        B_ = np.asarray(B_)
+        S, nu, d, k, st, its, nus = ref.coupled_iteration(A_, B_, iters, -1.0, keep_iterates=True)
+        G = np.zeros_like(S)
+        for i, j in enumerate(match):
+            if j >= 0:
+                G[i, j] = 1
+        dA_ = np.zeros_like(A_)
+        for kk in range(k - 1, -1, -1):
+            Yb = G / nus[kk]
+            dA_ += Yb.T @ B_ @ its[kk] + its[kk].T @ B_ @ Yb
+            G = B_.T @ Yb @ A_ + B_ @ Yb @ A_.T
+        return dA_, None
+    dA_bad, _ = no_projection(A, B, K, r.match)
+    assert not all(abs(fd(e) - dA_bad[ga.src[e], ga.dst[e]]) < 1e-8 for e in range(ga.nnz))
+    assert orig is ref.backward
+
+
+def test_mutant_resize_grid_fails_zoom_pin():
+    X = np.random.default_rng(2).random((5, 5))
+    Z = ndi.zoom(X, 9 / 5, order=1, grid_mode=False, mode="nearest")
+    good = oracle.resize_bilinear(X, 9)
+    assert np.allclose(good, Z, atol=1e-15)
+    # mutant: half-pixel-centred grid (grid_mode=True sampling)
+    from scipy.interpolate import RegularGridInterpolator
+    t = (np.arange(9) + 0.5) * 5 / 9 - 0.5
+    t = np.clip(t, 0, 4)
+    f = RegularGridInterpolator((np.arange(5), np.arange(5)), X)
+    P, Q = np.meshgrid(t, t, indexing="ij")
+    bad = f(np.stack([P.ravel(), Q.ravel()], axis=1)).reshape(9, 9)
+    assert not np.allclose(bad, Z, atol=1e-6)
+
+
+def test_pathfinder_fixture_invariants_both_modes():
+    """Figure 3 matrices as inputs (no printed output: parity unpinned)."""
+    m = pathfinder_fig3()
+    K, Mx = m["kepler"], m["maxwell"]
+    assert K.shape == (6, 6) and Mx.shape == (4, 4)
+    for mode in ("none", "bilinear"):
+        r = oracle.score_pair(Mx, K, resize=mode)
+        assert abs(np.linalg.norm(r.S) - 1) < 1e-14 and (r.S >= 0).all()
+        r2 = oracle.score_pair(K, Mx, resize=mode)
+        np.testing.assert_allclose(r2.S, r.S.T, atol=1e-13)
+        if mode == "bilinear":
+            assert r.S.shape == (6, 6)
+        else:
+            assert r.S.shape == (6, 4)
