@@ -1,0 +1,188 @@
+/*
+ * cfsim.h - C ABI of the CFG-pair coupled-similarity library (MI355X, gfx950).
+ *
+ * Method: Lim, Norris & Malony, "A Similarity Measure for GPU Kernel Subgraph
+ * Matching" (arXiv 1707.02423).  Two control-flow graphs are compared through
+ * their transition-probability matrices (Section 2, "Transition probability")
+ * by the IsoRank solution of their Kronecker operator (Table 1, row "Iso";
+ * Section 3.2), after an optional bilinear resize to a common size
+ * (Section 3, Section 3.1).
+ *
+ * What every entry point computes, for a pair (A, B) with n_A and n_B nodes:
+ *   S_0 = 1/sqrt(n_A n_B) (n_B x n_A, row i = node of B, column j = node of A)
+ *   Y_k = B S_k A^T + B^T S_k A,   S_{k+1} = Y_k / ||Y_k||_F
+ *   at even k: delta_k = ||S_k - S_{k-2}||_F; stop when delta_k < tol or
+ *   k = max_iter; return S_k.  Greedy matching on S (value descending, then
+ *   row-major flat index ascending), score = sum of matched entries.
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented "device" must point to device memory (or memory
+ *     the device can access); "host" pointers are read on the host before
+ *     the call returns.  The caller owns every buffer; the library allocates
+ *     no device memory in these calls (the context owns only cached launch
+ *     graphs).
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued
+ *     asynchronously; outputs are valid after the stream is synchronised.
+ *   - Return values: CFSIM_OK or a negative cfsim_status.  Argument errors
+ *     are detected on the host before any HIP call and leave all outputs
+ *     untouched; cfsim_last_error() then describes the problem.  Per-pair
+ *     conditions are not call errors: they are bits of cfsim_pair_result.status.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef CFSIM_H
+#define CFSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CFSIM_OK = 0,
+    CFSIM_E_INVALID_ARG = -1,   /* NULL pointer, bad size, bad option value   */
+    CFSIM_E_BAD_GRAPH = -2,     /* inconsistent graph description              */
+    CFSIM_E_NONFINITE = -3,     /* reserved for host-validated weights         */
+    CFSIM_E_NEGWEIGHT = -4,     /* reserved for host-validated weights         */
+    CFSIM_E_WORKSPACE = -5,     /* workspace smaller than the *_workspace_size */
+    CFSIM_E_UNSUPPORTED = -6,   /* valid request this build does not serve     */
+    CFSIM_E_HIP = -7            /* a HIP runtime call failed                   */
+} cfsim_status;
+
+/* Arithmetic type of S. */
+enum { CFSIM_F64 = 0, CFSIM_F32 = 1 };
+/* Scale-to-common-size step (Section 3, Section 3.1). */
+enum { CFSIM_RESIZE_NONE = 0, CFSIM_RESIZE_BILINEAR = 1 };
+
+/* Per-pair status bits (cfsim_pair_result.status). */
+#define CFSIM_CONVERGED     1u  /* an even-step delta fell below tol          */
+#define CFSIM_HIT_MAX_ITER  2u  /* stopped at max_iter                         */
+#define CFSIM_DEGENERATE    4u  /* A or B has no positive weight: S = S_0      */
+#define CFSIM_INVALID_INPUT 8u  /* pair skipped (bad index or size over limit) */
+
+/* Pack error bits written by cfsim_pack into *err_flags. */
+#define CFSIM_PACK_BAD_INDEX 1  /* a jump endpoint outside [0, n_g): dropped   */
+#define CFSIM_PACK_NONFINITE 2  /* a count is NaN or infinite: weight set to 0 */
+#define CFSIM_PACK_NEGATIVE  4  /* a count is negative: weight set to 0        */
+
+typedef struct {
+    int32_t dtype;      /* CFSIM_F64 or CFSIM_F32                                  */
+    int32_t max_iter;   /* K_max >= 1: maximum number of updates                   */
+    double tol;         /* stopping threshold on delta (>= 0; 0 = never converge)  */
+    int32_t resize;     /* CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR              */
+    uint32_t flags;     /* must be 0                                               */
+} cfsim_options;
+
+/* Result of one pair (device memory, 32 bytes). */
+typedef struct {
+    double score;       /* sum of S over the greedy matching                       */
+    double nu;          /* ||Y|| of the last update (tends to the spectral radius) */
+    double delta;       /* last even-step ||S_k - S_{k-2}||_F (inf if none)        */
+    int32_t iters;      /* number of updates applied (0 if degenerate)             */
+    uint32_t status;    /* CFSIM_* status bits                                     */
+} cfsim_pair_result;
+
+/*
+ * One graph: transition-probability matrix P (P[u][v] = weight of jump u->v)
+ * in CSR (successor lists) and CSC (predecessor lists) form.  n, nnz are host
+ * values; all arrays are device memory with 0-based local indices.
+ *   row_ptr[n+1], col[nnz], w[nnz]   successors of u: col[row_ptr[u]..row_ptr[u+1])
+ *   col_ptr[n+1], row[nnz], eid[nnz] predecessors of v: row[col_ptr[v]..], with
+ *                                    weight w[eid[t]] (eid = CSR position)
+ * cfsim_pack produces this layout; rows are sorted by column, columns by row.
+ */
+typedef struct {
+    int32_t n, nnz;
+    const int32_t* row_ptr;
+    const int32_t* col;
+    const double* w;
+    const int32_t* col_ptr;
+    const int32_t* row;
+    const int32_t* eid;
+} cfsim_graph;
+
+/*
+ * A packed set of graphs (device arrays; counts are host values).
+ * Graph g owns nodes [node_off[g], node_off[g+1]) and edges
+ * [edge_off[g], edge_off[g+1]); its row_ptr/col_ptr slices start at
+ * node_off[g] + g and hold n_g + 1 local offsets.  max_nodes is an upper
+ * bound of every n_g (used to size launches and workspaces).
+ */
+typedef struct {
+    int32_t n_graphs, max_nodes;
+    int64_t total_nodes, total_edges;
+    const int64_t* node_off;   /* [n_graphs+1] */
+    const int64_t* edge_off;   /* [n_graphs+1] */
+    const int32_t* row_ptr;    /* [total_nodes + n_graphs] */
+    const int32_t* col;        /* [total_edges] */
+    const double* w;           /* [total_edges] */
+    const int32_t* col_ptr;    /* [total_nodes + n_graphs] */
+    const int32_t* row;        /* [total_edges] */
+    const int32_t* eid;        /* [total_edges], local CSR position */
+} cfsim_graph_set;
+
+typedef struct cfsim_context cfsim_context;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* cfsim_last_error(void);
+/* Library version string. */
+const char* cfsim_version(void);
+
+/* Create a context bound to HIP device `device` (queries its properties). */
+cfsim_status cfsim_context_create(cfsim_context** out, int device);
+/* Destroy a context and its cached launch graphs (NULL is a no-op). */
+void cfsim_context_destroy(cfsim_context* ctx);
+
+/*
+ * Step a1 - transition probabilities (Section 2, "Transition probability"):
+ * build a graph set from jump lists with execution counts.  For graph g the
+ * jumps are src/dst/count[edge_off[g] .. edge_off[g+1]) with local node ids;
+ * w = count / (sum of counts of the same source); a row with zero total
+ * (the STOP node) stays zero.  Repeated jumps stay separate entries.
+ * Inputs node_off, edge_off, src, dst, count and outputs row_ptr .. eid,
+ * err_flags (one int32, overwritten) are device memory; ws is a device
+ * workspace of at least cfsim_pack_workspace_size() bytes.
+ */
+size_t cfsim_pack_workspace_size(int32_t n_graphs, int64_t total_nodes, int64_t total_edges);
+cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_nodes, int64_t total_edges,
+                        const int64_t* node_off, const int64_t* edge_off,
+                        const int32_t* src, const int32_t* dst, const double* count,
+                        int32_t* row_ptr, int32_t* col, double* w,
+                        int32_t* col_ptr, int32_t* row, int32_t* eid, int32_t* err_flags,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Steps a2-a7 for one pair (plain path, one launch): S_out (n_B x n_A
+ * row-major, opt->dtype; or n_M x n_M when resized), match_out[n_B] (or [n_M])
+ * and res[1] are device memory; S_out and match_out may be NULL.
+ */
+size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b,
+                                  const cfsim_options* opt);
+cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B,
+                         const cfsim_options* opt, void* S_out, int32_t* match_out,
+                         cfsim_pair_result* res, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Steps a2-a8 for many pairs (batched path): pair p compares A = graph
+ * pair_a[p] with B = graph pair_b[p] of `set`.  The pairs are planned on the
+ * device (size buckets, longest first) and run by persistent workgroups
+ * pulling from a device work queue; the launches are captured once into a
+ * HIP graph cached in the context and replayed while the arguments repeat.
+ * Device buffers: pair_a/pair_b[n_pairs], res[n_pairs]; optional (NULL to
+ * skip): match with match_off[n_pairs] (element offset of pair p's n_B
+ * entries), S_out with S_off[n_pairs] (element offset of pair p's S).
+ */
+size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set,
+                                  int64_t n_pairs, const cfsim_options* opt);
+cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
+                               const int32_t* pair_a, const int32_t* pair_b, int64_t n_pairs,
+                               const cfsim_options* opt, cfsim_pair_result* res,
+                               int32_t* match, const int64_t* match_off,
+                               void* S_out, const int64_t* S_off,
+                               void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFSIM_H */

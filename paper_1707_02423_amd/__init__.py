@@ -1,0 +1,9 @@
+"""cfsim: MI355X-native coupled similarity of CFG pairs (arXiv 1707.02423).
+
+The compute path is libcfsim.so (HIP kernels for gfx950, C ABI in
+include/cfsim.h); `cfsim.py` is the thin ctypes binding.
+"""
+from .cfsim import (  # noqa: F401
+    F32, F64, CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, RESULT_DTYPE,
+    Batch, CfsimError, Context, GraphSet, lib, options, pack, score, score_batch,
+)

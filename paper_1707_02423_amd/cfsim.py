@@ -1,0 +1,328 @@
+"""Python binding of libcfsim (argument marshalling only).
+
+Every step of the similarity runs in the HIP kernels of libcfsim.so; this
+module only moves arguments: it lays out device buffers with PyTorch (memory
+and streams), passes raw pointers through ctypes, and reads results back.
+There is no fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcfsim.so")
+
+F64, F32 = 0, 1
+RESIZE_NONE, RESIZE_BILINEAR = 0, 1
+CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT = 1, 2, 4, 8
+PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
+
+STATUS_NAMES = {0: "CFSIM_OK", -1: "CFSIM_E_INVALID_ARG", -2: "CFSIM_E_BAD_GRAPH", -3: "CFSIM_E_NONFINITE",
+                -4: "CFSIM_E_NEGWEIGHT", -5: "CFSIM_E_WORKSPACE", -6: "CFSIM_E_UNSUPPORTED", -7: "CFSIM_E_HIP"}
+
+RESULT_DTYPE = np.dtype([("score", "<f8"), ("nu", "<f8"), ("delta", "<f8"), ("iters", "<i4"), ("status", "<u4")])
+
+
+class CfsimError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("resize", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("w", ctypes.c_void_p), ("col_ptr", ctypes.c_void_p),
+                ("row", ctypes.c_void_p), ("eid", ctypes.c_void_p)]
+
+
+class GraphSetC(ctypes.Structure):
+    _fields_ = [("n_graphs", ctypes.c_int32), ("max_nodes", ctypes.c_int32), ("total_nodes", ctypes.c_int64),
+                ("total_edges", ctypes.c_int64), ("node_off", ctypes.c_void_p), ("edge_off", ctypes.c_void_p),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("w", ctypes.c_void_p),
+                ("col_ptr", ctypes.c_void_p), ("row", ctypes.c_void_p), ("eid", ctypes.c_void_p)]
+
+
+_LIB = None
+_P = ctypes.c_void_p
+_SZ = ctypes.c_size_t
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+
+# name -> (restype, argtypes); must mirror include/cfsim.h
+SIGNATURES = {
+    "cfsim_last_error": (ctypes.c_char_p, []),
+    "cfsim_version": (ctypes.c_char_p, []),
+    "cfsim_context_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int]),
+    "cfsim_context_destroy": (None, [_P]),
+    "cfsim_pack_workspace_size": (_SZ, [_I32, _I64, _I64]),
+    "cfsim_pack": (ctypes.c_int, [_P, _I32, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ,
+                                  _P]),
+    "cfsim_score_workspace_size": (_SZ, [_P, _I32, _I32, ctypes.POINTER(Options)]),
+    "cfsim_score": (ctypes.c_int, [_P, ctypes.POINTER(Graph), ctypes.POINTER(Graph), ctypes.POINTER(Options), _P, _P,
+                                   _P, _P, _SZ, _P]),
+    "cfsim_batch_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options)]),
+    "cfsim_score_batch": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
+                                         _P, _P, _P, _P, _P, _SZ, _P]),
+}
+
+
+def lib():
+    """The loaded libcfsim.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1707_02423_amd/build.py "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int):
+    if code != 0:
+        raise CfsimError(code, lib().cfsim_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream or None
+
+
+def options(dtype="f64", max_iter=200, tol=1e-12, resize="none") -> Options:
+    d = {"f64": F64, "f32": F32}[dtype] if isinstance(dtype, str) else int(dtype)
+    r = {"none": RESIZE_NONE, "bilinear": RESIZE_BILINEAR}[resize] if isinstance(resize, str) else int(resize)
+    return Options(dtype=d, max_iter=int(max_iter), tol=float(tol), resize=r, flags=0)
+
+
+class Context:
+    """A libcfsim context bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _P()
+        _check(lib().cfsim_context_create(ctypes.byref(h), int(device)))
+        self.handle = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cfsim_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class GraphSet:
+    """A packed, device-resident set of graphs (output of `pack`)."""
+    n_graphs: int
+    max_nodes: int
+    node_off: np.ndarray   # host copy, int64 [G+1]
+    edge_off: np.ndarray   # host copy, int64 [G+1]
+    d_node_off: torch.Tensor
+    d_edge_off: torch.Tensor
+    row_ptr: torch.Tensor
+    col: torch.Tensor
+    w: torch.Tensor
+    col_ptr: torch.Tensor
+    row: torch.Tensor
+    eid: torch.Tensor
+
+    @property
+    def total_nodes(self) -> int:
+        return int(self.node_off[-1])
+
+    @property
+    def total_edges(self) -> int:
+        return int(self.edge_off[-1])
+
+    def sizes(self) -> np.ndarray:
+        return np.diff(self.node_off)
+
+    def c_struct(self, w: torch.Tensor | None = None) -> GraphSetC:
+        w = self.w if w is None else w
+        return GraphSetC(self.n_graphs, self.max_nodes, self.total_nodes, self.total_edges,
+                         _ptr(self.d_node_off), _ptr(self.d_edge_off), _ptr(self.row_ptr), _ptr(self.col), _ptr(w),
+                         _ptr(self.col_ptr), _ptr(self.row), _ptr(self.eid))
+
+    def graph(self, g: int) -> Graph:
+        """A cfsim_graph view of graph g (pointers into the packed arrays)."""
+        n0, n1 = int(self.node_off[g]), int(self.node_off[g + 1])
+        e0, e1 = int(self.edge_off[g]), int(self.edge_off[g + 1])
+        i4, f8 = 4, 8
+        return Graph(n1 - n0, e1 - e0,
+                     self.row_ptr.data_ptr() + (n0 + g) * i4, self.col.data_ptr() + e0 * i4,
+                     self.w.data_ptr() + e0 * f8, self.col_ptr.data_ptr() + (n0 + g) * i4,
+                     self.row.data_ptr() + e0 * i4, self.eid.data_ptr() + e0 * i4)
+
+    def host_csr(self, g: int):
+        """(row_ptr, col, w) of graph g copied to the host."""
+        n0, n1 = int(self.node_off[g]), int(self.node_off[g + 1])
+        e0, e1 = int(self.edge_off[g]), int(self.edge_off[g + 1])
+        return (self.row_ptr[n0 + g:n1 + g + 1].cpu().numpy(), self.col[e0:e1].cpu().numpy(),
+                self.w[e0:e1].cpu().numpy())
+
+
+def concat_coo(graphs):
+    """Concatenate per-graph jump lists (objects with n, src, dst, count)."""
+    ns = np.array([g.n for g in graphs], np.int64)
+    ms = np.array([len(g.src) for g in graphs], np.int64)
+    node_off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    edge_off = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    src = np.concatenate([np.asarray(g.src, np.int32) for g in graphs]) if graphs else np.zeros(0, np.int32)
+    dst = np.concatenate([np.asarray(g.dst, np.int32) for g in graphs]) if graphs else np.zeros(0, np.int32)
+    cnt = np.concatenate([np.asarray(g.count, np.float64) for g in graphs]) if graphs else np.zeros(0)
+    return node_off, edge_off, src, dst, cnt
+
+
+def pack(ctx: Context, graphs, device=None, stream=None, check=True) -> GraphSet:
+    """Step a1 on the device: jump lists with counts -> CSR/CSC transition matrices."""
+    dev = torch.device("cuda", ctx.device) if device is None else torch.device(device)
+    node_off, edge_off, src, dst, cnt = concat_coo(graphs)
+    G = len(graphs)
+    N, E = int(node_off[-1]), int(edge_off[-1])
+    t = lambda a, dt: torch.as_tensor(a, dtype=dt).to(dev)
+    d_node_off, d_edge_off = t(node_off, torch.int64), t(edge_off, torch.int64)
+    d_src, d_dst, d_cnt = t(src, torch.int32), t(dst, torch.int32), t(cnt, torch.float64)
+    rp = torch.empty(N + G, dtype=torch.int32, device=dev)
+    cp = torch.empty(N + G, dtype=torch.int32, device=dev)
+    col = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    row = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    eid = torch.empty(max(E, 1), dtype=torch.int32, device=dev)
+    w = torch.empty(max(E, 1), dtype=torch.float64, device=dev)
+    err = torch.zeros(1, dtype=torch.int32, device=dev)
+    ws_bytes = lib().cfsim_pack_workspace_size(G, N, E)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().cfsim_pack(ctx.handle, G, N, E, _ptr(d_node_off), _ptr(d_edge_off), _ptr(d_src), _ptr(d_dst),
+                            _ptr(d_cnt), _ptr(rp), _ptr(col), _ptr(w), _ptr(cp), _ptr(row), _ptr(eid), _ptr(err),
+                            _ptr(ws), ws_bytes, _stream(stream)))
+    if check:
+        flags = int(err.item())
+        if flags:
+            raise ValueError(f"cfsim_pack flagged the input (bits {flags:#x}: 1 = bad node id, "
+                             "2 = non-finite count, 4 = negative count)")
+    max_nodes = int(np.diff(node_off).max()) if G else 1
+    return GraphSet(G, max(max_nodes, 1), node_off, edge_off, d_node_off, d_edge_off, rp, col, w, cp, row, eid)
+
+
+def _torch_dtype(opt: Options):
+    return torch.float64 if opt.dtype == F64 else torch.float32
+
+
+def score(ctx: Context, gs: GraphSet, a: int, b: int, dtype="f64", max_iter=200, tol=1e-12, resize="none",
+          want_S=True, stream=None, sync=True):
+    """Plain path, one pair: A = graph a, B = graph b of the set."""
+    opt = options(dtype, max_iter, tol, resize)
+    A, B = gs.graph(a), gs.graph(b)
+    dev = gs.w.device
+    S = torch.empty(B.n * A.n, dtype=_torch_dtype(opt), device=dev) if want_S else None
+    match = torch.empty(B.n, dtype=torch.int32, device=dev)
+    res = torch.empty(32, dtype=torch.uint8, device=dev)
+    ws_bytes = lib().cfsim_score_workspace_size(ctx.handle, A.n, B.n, ctypes.byref(opt))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().cfsim_score(ctx.handle, ctypes.byref(A), ctypes.byref(B), ctypes.byref(opt), _ptr(S), _ptr(match),
+                             _ptr(res), _ptr(ws), ws_bytes, _stream(stream)))
+    out = dict(S=S, match=match, res=res)
+    if sync:
+        return finish_single(out, B.n, A.n)
+    return out
+
+
+def finish_single(out, nB, nA):
+    r = out["res"].cpu().numpy().view(RESULT_DTYPE)[0]
+    d = {k: r[k].item() for k in RESULT_DTYPE.names}
+    d["match"] = out["match"].cpu().numpy()
+    if out["S"] is not None:
+        d["S"] = out["S"].cpu().numpy().reshape(nB, nA)
+    return d
+
+
+class Batch:
+    """Pre-allocated buffers for repeated batched scoring of a fixed pair list.
+
+    `run()` enqueues one batched call (a replay of the cached HIP graph after
+    the first call) on the current stream and returns immediately.
+    """
+
+    def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
+                 resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None):
+        self.ctx, self.gs = ctx, gs
+        self.opt = options(dtype, max_iter, tol, resize)
+        dev = gs.w.device
+        self.pair_a_h = np.asarray(pair_a, np.int32)
+        self.pair_b_h = np.asarray(pair_b, np.int32)
+        self.n_pairs = int(self.pair_a_h.shape[0])
+        self.pair_a = torch.as_tensor(self.pair_a_h).to(dev)
+        self.pair_b = torch.as_tensor(self.pair_b_h).to(dev)
+        self.res = torch.empty(max(self.n_pairs, 1) * 32, dtype=torch.uint8, device=dev)
+        sizes = gs.sizes().astype(np.int64)
+
+        def size_of(idx):  # 0 for ids outside the set (the kernel marks those pairs invalid)
+            ok = (idx >= 0) & (idx < gs.n_graphs)
+            return np.where(ok, sizes[np.clip(idx, 0, gs.n_graphs - 1)], 0).astype(np.int64)
+        nA, nB = size_of(self.pair_a_h), size_of(self.pair_b_h)
+        self.nA, self.nB = nA, nB
+        self.match = self.match_off = self.S = self.S_off = None
+        if want_match:
+            off = np.concatenate([[0], np.cumsum(nB)]).astype(np.int64)
+            self.match_off_h = off[:-1]
+            self.match_off = torch.as_tensor(self.match_off_h).to(dev)
+            self.match = torch.empty(max(int(off[-1]), 1), dtype=torch.int32, device=dev)
+        if want_S:
+            off = np.concatenate([[0], np.cumsum(nA * nB)]).astype(np.int64)
+            self.S_off_h = off[:-1]
+            self.S_off = torch.as_tensor(self.S_off_h).to(dev)
+            self.S = torch.empty(max(int(off[-1]), 1), dtype=_torch_dtype(self.opt), device=dev)
+        self.w = w
+        self.set_c = gs.c_struct(w)
+        self.ws_bytes = lib().cfsim_batch_workspace_size(ctx.handle, ctypes.byref(self.set_c), self.n_pairs,
+                                                         ctypes.byref(self.opt))
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
+
+    def run(self, stream=None):
+        _check(lib().cfsim_score_batch(self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a),
+                                       _ptr(self.pair_b), self.n_pairs, ctypes.byref(self.opt), _ptr(self.res),
+                                       _ptr(self.match), _ptr(self.match_off), _ptr(self.S), _ptr(self.S_off),
+                                       _ptr(self.ws), self.ws_bytes, _stream(stream)))
+
+    def results(self) -> np.ndarray:
+        return self.res[: self.n_pairs * 32].cpu().numpy().view(RESULT_DTYPE)
+
+    def matches(self):
+        m = self.match.cpu().numpy()
+        return [m[o:o + n] for o, n in zip(self.match_off_h, self.nB)]
+
+    def S_list(self):
+        S = self.S.cpu().numpy()
+        return [S[o:o + a * b].reshape(b, a) for o, a, b in zip(self.S_off_h, self.nA, self.nB)]
+
+
+def score_batch(ctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, resize="none", want_match=True,
+                want_S=False):
+    """Batched path: run once, synchronise, return (results, matches, S list)."""
+    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S)
+    b.run()
+    torch.cuda.synchronize()
+    return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)

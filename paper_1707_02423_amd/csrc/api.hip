@@ -1,0 +1,420 @@
+// Host side of the C ABI declared in include/cfsim.h: argument validation
+// (always before any HIP call), the context, workspace carving, the batch
+// plan / persistent launches, and the HIP-graph cache of the batched path.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "cfsim_internal.h"
+
+struct cfsim_context {
+    int device = 0;
+    int num_cus = 0;
+    int grid[2][cfsim::kNumVariants] = {};  // persistent grid per [dtype][variant]
+    hipStream_t cap = nullptr;              // capture stream of the batch graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> key;         // arguments the cached graph was built for
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+cfsim_status fail(cfsim_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+cfsim_status ok() {
+    g_err.clear();
+    return CFSIM_OK;
+}
+
+cfsim_status hip_fail(int e, const char* what) {
+    return fail(CFSIM_E_HIP, "%s: %s", what, hipGetErrorString((hipError_t)e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+cfsim_status check_options(const cfsim_options* o) {
+    if (!o) return fail(CFSIM_E_INVALID_ARG, "options pointer is NULL");
+    if (o->dtype != CFSIM_F64 && o->dtype != CFSIM_F32)
+        return fail(CFSIM_E_INVALID_ARG, "dtype must be CFSIM_F64 or CFSIM_F32 (got %d)", o->dtype);
+    if (o->max_iter < 1) return fail(CFSIM_E_INVALID_ARG, "max_iter must be >= 1 (got %d)", o->max_iter);
+    if (!(o->tol >= 0.0) || !std::isfinite(o->tol))
+        return fail(CFSIM_E_INVALID_ARG, "tol must be finite and >= 0");
+    if (o->resize != CFSIM_RESIZE_NONE && o->resize != CFSIM_RESIZE_BILINEAR)
+        return fail(CFSIM_E_INVALID_ARG, "resize must be CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR");
+    if (o->flags != 0) return fail(CFSIM_E_INVALID_ARG, "flags must be 0");
+    if (o->resize == CFSIM_RESIZE_BILINEAR)
+        return fail(CFSIM_E_UNSUPPORTED, "bilinear resize is not available in this build");
+    return CFSIM_OK;
+}
+
+cfsim_status check_graph(const cfsim_graph* g, const char* name) {
+    if (!g) return fail(CFSIM_E_INVALID_ARG, "graph %s is NULL", name);
+    if (g->n < 1) return fail(CFSIM_E_BAD_GRAPH, "graph %s: n must be >= 1 (got %d)", name, g->n);
+    if (g->nnz < 0) return fail(CFSIM_E_BAD_GRAPH, "graph %s: nnz must be >= 0", name);
+    if (!g->row_ptr || !g->col_ptr) return fail(CFSIM_E_INVALID_ARG, "graph %s: row_ptr/col_ptr is NULL", name);
+    if (g->nnz > 0 && (!g->col || !g->w || !g->row || !g->eid))
+        return fail(CFSIM_E_INVALID_ARG, "graph %s: an edge array is NULL", name);
+    return CFSIM_OK;
+}
+
+cfsim_status check_set(const cfsim_graph_set* s) {
+    if (!s) return fail(CFSIM_E_INVALID_ARG, "graph set is NULL");
+    if (s->n_graphs < 1) return fail(CFSIM_E_BAD_GRAPH, "graph set: n_graphs must be >= 1");
+    if (s->max_nodes < 1) return fail(CFSIM_E_BAD_GRAPH, "graph set: max_nodes must be >= 1");
+    if (s->total_nodes < s->n_graphs || s->total_edges < 0)
+        return fail(CFSIM_E_BAD_GRAPH, "graph set: bad total_nodes/total_edges");
+    if (!s->node_off || !s->edge_off || !s->row_ptr || !s->col_ptr)
+        return fail(CFSIM_E_INVALID_ARG, "graph set: an offset array is NULL");
+    if (s->total_edges > 0 && (!s->col || !s->w || !s->row || !s->eid))
+        return fail(CFSIM_E_INVALID_ARG, "graph set: an edge array is NULL");
+    return CFSIM_OK;
+}
+
+cfsim::GraphRef ref_of(const cfsim_graph* g) {
+    cfsim::GraphRef r;
+    r.n = g->n;
+    r.nnz = g->nnz;
+    r.rp = g->row_ptr;
+    r.ci = g->col;
+    r.w = g->w;
+    r.cp = g->col_ptr;
+    r.ri = g->row;
+    r.eid = g->eid;
+    return r;
+}
+
+cfsim::SetRef ref_of(const cfsim_graph_set* s) {
+    cfsim::SetRef r;
+    r.node_off = s->node_off;
+    r.edge_off = s->edge_off;
+    r.rp = s->row_ptr;
+    r.ci = s->col;
+    r.w = s->w;
+    r.cp = s->col_ptr;
+    r.ri = s->row;
+    r.eid = s->eid;
+    r.n_graphs = s->n_graphs;
+    return r;
+}
+
+int dtype_index(int dtype) { return dtype == CFSIM_F64 ? 0 : 1; }
+int esize_of(int dtype) { return dtype == CFSIM_F64 ? 8 : 4; }
+
+// Batch workspace: order[n_pairs] | bounds[2*(V+1)] | queues[V+1]
+struct BatchWs {
+    int32_t* order;
+    int32_t* bounds;
+    int32_t* queues;
+};
+size_t batch_ws_bytes(int64_t n_pairs) {
+    return align256((size_t)n_pairs * 4) + align256(2 * (cfsim::kNumVariants + 1) * 4) +
+           align256((cfsim::kNumVariants + 1) * 4);
+}
+BatchWs carve_batch(void* ws, int64_t n_pairs) {
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    BatchWs b;
+    b.order = reinterpret_cast<int32_t*>(p);
+    p += align256((size_t)n_pairs * 4);
+    b.bounds = reinterpret_cast<int32_t*>(p);
+    p += align256(2 * (cfsim::kNumVariants + 1) * 4);
+    b.queues = reinterpret_cast<int32_t*>(p);
+    return b;
+}
+
+template <typename X>
+void append_key(std::vector<unsigned char>& k, const X& x) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
+    k.insert(k.end(), p, p + sizeof(X));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cfsim_last_error(void) { return g_err.c_str(); }
+
+const char* cfsim_version(void) { return "cfsim 0.1.0 gfx950"; }
+
+cfsim_status cfsim_context_create(cfsim_context** out, int device) {
+    if (!out) return fail(CFSIM_E_INVALID_ARG, "out pointer is NULL");
+    *out = nullptr;
+    int count = 0;
+    int e = (int)hipGetDeviceCount(&count);
+    if (e != 0) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(CFSIM_E_INVALID_ARG, "device %d out of range [0,%d)", device, count);
+    if ((e = (int)hipSetDevice(device)) != 0) return hip_fail(e, "hipSetDevice");
+    cfsim_context* ctx = new cfsim_context();
+    ctx->device = device;
+    if ((e = (int)hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device)) != 0) {
+        delete ctx;
+        return hip_fail(e, "hipDeviceGetAttribute");
+    }
+    if ((e = cfsim::set_kernel_attributes()) != 0) {
+        delete ctx;
+        return hip_fail(e, "hipFuncSetAttribute");
+    }
+    for (int d = 0; d < 2; ++d) {
+        for (int v = 0; v < cfsim::kNumVariants; ++v) {
+            int blocks = 0;
+            if ((e = cfsim::occupancy_of(v, d == 0 ? CFSIM_F64 : CFSIM_F32, &blocks)) != 0) {
+                delete ctx;
+                return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
+            }
+            ctx->grid[d][v] = ctx->num_cus * (blocks > 0 ? blocks : 1);
+        }
+    }
+    if ((e = (int)hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)) != 0) {
+        delete ctx;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    *out = ctx;
+    return ok();
+}
+
+void cfsim_context_destroy(cfsim_context* ctx) {
+    if (!ctx) return;
+    if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    delete ctx;
+}
+
+// ------------------------------------------------------------------ pack (a1)
+size_t cfsim_pack_workspace_size(int32_t n_graphs, int64_t total_nodes, int64_t total_edges) {
+    (void)n_graphs;
+    if (total_nodes < 0 || total_edges < 0) return 0;
+    return align256((size_t)total_nodes * 4) + 2 * align256((size_t)total_edges * 4);
+}
+
+cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_nodes, int64_t total_edges,
+                        const int64_t* node_off, const int64_t* edge_off, const int32_t* src, const int32_t* dst,
+                        const double* count, int32_t* row_ptr, int32_t* col, double* w, int32_t* col_ptr,
+                        int32_t* row, int32_t* eid, int32_t* err_flags, void* ws, size_t ws_bytes, void* stream) {
+    if (n_graphs < 0) return fail(CFSIM_E_INVALID_ARG, "n_graphs must be >= 0");
+    if (total_nodes < 0 || total_edges < 0) return fail(CFSIM_E_INVALID_ARG, "totals must be >= 0");
+    if (total_nodes > INT32_MAX || total_edges > INT32_MAX)
+        return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 nodes or edges in one set");
+    if (!node_off || !edge_off || !row_ptr || !col_ptr || !err_flags)
+        return fail(CFSIM_E_INVALID_ARG, "an offset or output array is NULL");
+    if (total_edges > 0 && (!src || !dst || !count || !col || !w || !row || !eid))
+        return fail(CFSIM_E_INVALID_ARG, "an edge array is NULL");
+    const size_t need = cfsim_pack_workspace_size(n_graphs, total_nodes, total_edges);
+    if (ws_bytes < need || (need > 0 && !ws))
+        return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    cfsim::PackJob job;
+    job.n_graphs = n_graphs;
+    job.node_off = node_off;
+    job.edge_off = edge_off;
+    job.src = src;
+    job.dst = dst;
+    job.count = count;
+    job.rp = row_ptr;
+    job.ci = col;
+    job.w = w;
+    job.cp = col_ptr;
+    job.ri = row;
+    job.eid = eid;
+    job.err = err_flags;
+    job.cursor = reinterpret_cast<int32_t*>(p);
+    p += align256((size_t)total_nodes * 4);
+    job.eorig = reinterpret_cast<int32_t*>(p);
+    p += align256((size_t)total_edges * 4);
+    job.csrpos = reinterpret_cast<int32_t*>(p);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    e = cfsim::launch_pack(job, static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "pack launch");
+    return ok();
+}
+
+// ------------------------------------------------------------------ plain pair (a2-a7)
+size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b, const cfsim_options* opt) {
+    (void)ctx;
+    (void)n_a;
+    (void)n_b;
+    (void)opt;
+    return 0;
+}
+
+cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B, const cfsim_options* opt,
+                         void* S_out, int32_t* match_out, cfsim_pair_result* res, void* ws, size_t ws_bytes,
+                         void* stream) {
+    (void)ws;
+    (void)ws_bytes;
+    cfsim_status s;
+    if ((s = check_graph(A, "A")) != CFSIM_OK) return s;
+    if ((s = check_graph(B, "B")) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
+    const int esize = esize_of(opt->dtype);
+    int variant = -1;
+    cfsim::PairShape sh;
+    for (int v = 0; v < cfsim::kNumVariants && variant < 0; ++v)
+        if (cfsim::choose_shape(A->n, B->n, A->nnz, B->nnz, v, esize, &sh)) variant = v;
+    if (variant < 0)
+        return fail(CFSIM_E_UNSUPPORTED, "pair %d x %d does not fit the LDS-resident kernel", B->n, A->n);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    cfsim::PairJob job{};
+    job.single = 1;
+    job.ga = ref_of(A);
+    job.gb = ref_of(B);
+    job.max_iter = opt->max_iter;
+    job.tol = opt->tol;
+    job.res = res;
+    job.match = match_out;
+    job.S_out = S_out;
+    job.variant = variant;
+    job.lds_bytes = cfsim::variant_info(variant, esize).lds_bytes;
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    e = cfsim::launch_pair_lds(variant, opt->dtype, job, 1, static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "pair kernel launch");
+    return ok();
+}
+
+// ------------------------------------------------------------------ batch (a2-a8)
+size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
+                                  const cfsim_options* opt) {
+    (void)ctx;
+    (void)set;
+    (void)opt;
+    if (n_pairs < 0) return 0;
+    return batch_ws_bytes(n_pairs);
+}
+
+static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                         hipStream_t st) {
+    const BatchWs b = carve_batch(ws, n_pairs);
+    cfsim::PlanJob plan;
+    plan.set = ref_of(set);
+    plan.pair_a = pair_a;
+    plan.pair_b = pair_b;
+    plan.n_pairs = n_pairs;
+    plan.esize = esize_of(opt->dtype);
+    plan.order = b.order;
+    plan.bounds = b.bounds;
+    plan.queues = b.queues;
+    int e = cfsim::launch_plan(plan, st);
+    if (e != 0) return e;
+    cfsim::PairJob job{};
+    job.single = 0;
+    job.set = ref_of(set);
+    job.pair_a = pair_a;
+    job.pair_b = pair_b;
+    job.order = b.order;
+    job.max_iter = opt->max_iter;
+    job.tol = opt->tol;
+    job.res = res;
+    job.match = match;
+    job.match_off = match_off;
+    job.S_out = S_out;
+    job.S_off = S_off;
+    const int d = dtype_index(opt->dtype);
+    // largest pairs first: bucket V-1 down to 0, then the pairs no bucket holds
+    for (int v = cfsim::kNumVariants - 1; v >= 0; --v) {
+        job.variant = v;
+        job.lds_bytes = cfsim::variant_info(v, esize_of(opt->dtype)).lds_bytes;
+        job.bounds = b.bounds + 2 * v;
+        job.queue = b.queues + v;
+        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, ctx->grid[d][v], st)) != 0) return e;
+    }
+    job.bounds = b.bounds + 2 * cfsim::kNumVariants;
+    job.queue = b.queues + cfsim::kNumVariants;
+    return cfsim::launch_pair_lds(cfsim::kNumVariants, opt->dtype, job, 1, st);
+}
+
+cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                               const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                               cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                               const int64_t* S_off, void* ws, size_t ws_bytes, void* stream) {
+    cfsim_status s;
+    if ((s = check_set(set)) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
+    if (n_pairs > 0 && (!pair_a || !pair_b || !res))
+        return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or res is NULL");
+    if ((match == nullptr) != (match_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
+    if ((S_out == nullptr) != (S_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
+    const size_t need = batch_ws_bytes(n_pairs);
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_pairs == 0) return ok();
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    const char* nog = getenv("CFSIM_NO_GRAPH");
+    if (nog && nog[0] == '1') {
+        e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+        if (e != 0) return hip_fail(e, "batch launch");
+        return ok();
+    }
+
+    std::vector<unsigned char> key;
+    append_key(key, *set);
+    append_key(key, pair_a);
+    append_key(key, pair_b);
+    append_key(key, n_pairs);
+    append_key(key, *opt);
+    append_key(key, res);
+    append_key(key, match);
+    append_key(key, match_off);
+    append_key(key, S_out);
+    append_key(key, S_off);
+    append_key(key, ws);
+    if (!ctx->exec || key != ctx->key) {
+        if (ctx->exec) {
+            (void)hipGraphExecDestroy(ctx->exec);
+            ctx->exec = nullptr;
+        }
+        if (ctx->graph) {
+            (void)hipGraphDestroy(ctx->graph);
+            ctx->graph = nullptr;
+        }
+        ctx->key.clear();
+        if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
+            return hip_fail(e, "hipStreamBeginCapture");
+        const int le = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
+                                     ws, ctx->cap);
+        hipGraph_t g = nullptr;
+        e = (int)hipStreamEndCapture(ctx->cap, &g);
+        if (le != 0) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le, "batch launch during capture");
+        }
+        if (e != 0) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        if ((e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != 0) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ctx->graph = g;
+        ctx->exec = x;
+        ctx->key = key;
+    }
+    if ((e = (int)hipGraphLaunch(ctx->exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
+    return ok();
+}
+
+}  // extern "C"
