@@ -14,8 +14,11 @@
 struct cfsim_context {
     int device = 0;
     int num_cus = 0;
-    int grid[2][cfsim::kNumVariants] = {};  // persistent grid per [dtype][variant]
+    int grid[2][cfsim::kBucketGlobal + 1] = {};  // persistent grid per [dtype][LDS variant | global]
     hipStream_t cap = nullptr;              // capture stream of the batch graph
+    hipStream_t side[cfsim::kBuckets] = {};  // one stream per bucket (fork/join)
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[cfsim::kBuckets] = {};
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> key;         // arguments the cached graph was built for
@@ -114,24 +117,54 @@ cfsim::SetRef ref_of(const cfsim_graph_set* s) {
 int dtype_index(int dtype) { return dtype == CFSIM_F64 ? 0 : 1; }
 int esize_of(int dtype) { return dtype == CFSIM_F64 ? 8 : 4; }
 
-// Batch workspace: order[n_pairs] | bounds[2*(V+1)] | queues[V+1]
+// Workgroups per CU the LDS budget of a kernel allows (an upper bound of the
+// persistent grid, used to size workspaces before a context exists).
+int lds_blocks_per_cu(int v, int esize) {
+    const int lds = v == cfsim::kBucketGlobal ? cfsim::kGlobalLds : cfsim::variant_info(v, esize).lds_bytes;
+    const int nt = v == cfsim::kBucketGlobal ? cfsim::kGlobalThreads : cfsim::variant_info(v, esize).nt;
+    const int by_lds = (160 * 1024) / (lds + 1024);
+    const int by_waves = (4 * 4) / (nt / 64 > 0 ? nt / 64 : 1);  // 4 waves per SIMD
+    const int b = by_lds < by_waves ? by_lds : by_waves;
+    return b > 0 ? b : 1;
+}
+
+int num_cus_of(const cfsim_context* ctx) { return ctx && ctx->num_cus > 0 ? ctx->num_cus : 256; }
+
+// Elements of one global-kernel slot (each of S_cur, S_next, S_{k-2}).
+long long global_slot_elems(int max_nodes) { return (long long)max_nodes * (long long)max_nodes; }
+
+// Batch workspace: order[n_pairs] | bounds[2*kBuckets] | queues[kBuckets]
+//   | per LDS variant v: grid slots of variant_slot_elems(v) (S_{k-2})
+//   | global kernel: grid slots of 3 * global_slot_elems
 struct BatchWs {
     int32_t* order;
     int32_t* bounds;
     int32_t* queues;
+    void* slots[cfsim::kBucketGlobal + 1];
 };
-size_t batch_ws_bytes(int64_t n_pairs) {
-    return align256((size_t)n_pairs * 4) + align256(2 * (cfsim::kNumVariants + 1) * 4) +
-           align256((cfsim::kNumVariants + 1) * 4);
+size_t slot_bytes(const cfsim_context* ctx, int v, int esize, int max_nodes) {
+    const size_t wgs = (size_t)num_cus_of(ctx) * (size_t)lds_blocks_per_cu(v, esize);
+    if (v == cfsim::kBucketGlobal) return align256(wgs * 3 * (size_t)global_slot_elems(max_nodes) * esize);
+    return align256(wgs * (size_t)cfsim::variant_slot_elems(v, esize) * esize);
 }
-BatchWs carve_batch(void* ws, int64_t n_pairs) {
+size_t batch_ws_bytes(const cfsim_context* ctx, int64_t n_pairs, int esize, int max_nodes) {
+    size_t b = align256((size_t)n_pairs * 4) + align256(2 * cfsim::kBuckets * 4) + align256(cfsim::kBuckets * 4);
+    for (int v = 0; v <= cfsim::kBucketGlobal; ++v) b += slot_bytes(ctx, v, esize, max_nodes);
+    return b;
+}
+BatchWs carve_batch(const cfsim_context* ctx, void* ws, int64_t n_pairs, int esize, int max_nodes) {
     unsigned char* p = static_cast<unsigned char*>(ws);
     BatchWs b;
     b.order = reinterpret_cast<int32_t*>(p);
     p += align256((size_t)n_pairs * 4);
     b.bounds = reinterpret_cast<int32_t*>(p);
-    p += align256(2 * (cfsim::kNumVariants + 1) * 4);
+    p += align256(2 * cfsim::kBuckets * 4);
     b.queues = reinterpret_cast<int32_t*>(p);
+    p += align256(cfsim::kBuckets * 4);
+    for (int v = 0; v <= cfsim::kBucketGlobal; ++v) {
+        b.slots[v] = p;
+        p += slot_bytes(ctx, v, esize, max_nodes);
+    }
     return b;
 }
 
@@ -168,18 +201,29 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device) {
         return hip_fail(e, "hipFuncSetAttribute");
     }
     for (int d = 0; d < 2; ++d) {
-        for (int v = 0; v < cfsim::kNumVariants; ++v) {
+        for (int v = 0; v <= cfsim::kBucketGlobal; ++v) {
             int blocks = 0;
             if ((e = cfsim::occupancy_of(v, d == 0 ? CFSIM_F64 : CFSIM_F32, &blocks)) != 0) {
                 delete ctx;
                 return hip_fail(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
             }
-            ctx->grid[d][v] = ctx->num_cus * (blocks > 0 ? blocks : 1);
+            const int cap = lds_blocks_per_cu(v, d == 0 ? 8 : 4);
+            blocks = blocks < 1 ? 1 : (blocks > cap ? cap : blocks);
+            ctx->grid[d][v] = ctx->num_cus * blocks;
         }
     }
     if ((e = (int)hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)) != 0) {
         delete ctx;
         return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    e = (int)hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+    for (int v = 0; v < cfsim::kBuckets && e == 0; ++v) {
+        e = (int)hipStreamCreateWithFlags(&ctx->side[v], hipStreamNonBlocking);
+        if (e == 0) e = (int)hipEventCreateWithFlags(&ctx->join[v], hipEventDisableTiming);
+    }
+    if (e != 0) {
+        cfsim_context_destroy(ctx);
+        return hip_fail(e, "stream/event creation");
     }
     *out = ctx;
     return ok();
@@ -190,6 +234,11 @@ void cfsim_context_destroy(cfsim_context* ctx) {
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    for (int v = 0; v < cfsim::kBuckets; ++v) {
+        if (ctx->side[v]) (void)hipStreamDestroy(ctx->side[v]);
+        if (ctx->join[v]) (void)hipEventDestroy(ctx->join[v]);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
 }
 
@@ -244,31 +293,38 @@ cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_node
 }
 
 // ------------------------------------------------------------------ plain pair (a2-a7)
+// The plain path picks the first LDS variant that holds the pair, else the
+// global-memory kernel; -1 if neither can take it.
+static int plain_variant(int nA, int nB, int nnzA, int nnzB, int esize, cfsim::PairShape* sh) {
+    for (int v = 0; v < cfsim::kNumVariants; ++v)
+        if (cfsim::choose_shape(nA, nB, nnzA, nnzB, v, esize, sh)) return v;
+    if (cfsim::global_fits(nA, nB, nnzA, nnzB, esize, (long long)nA * nB, sh)) return cfsim::kBucketGlobal;
+    return -1;
+}
+
 size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b, const cfsim_options* opt) {
     (void)ctx;
-    (void)n_a;
-    (void)n_b;
-    (void)opt;
-    return 0;
+    if (n_a < 1 || n_b < 1 || !opt) return 0;
+    const size_t esize = esize_of(opt->dtype);
+    // S_{k-2} slot (LDS kernels) or S_cur, S_next, S_{k-2} (global kernel)
+    return align256(3 * (size_t)n_a * (size_t)n_b * esize);
 }
 
 cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B, const cfsim_options* opt,
                          void* S_out, int32_t* match_out, cfsim_pair_result* res, void* ws, size_t ws_bytes,
                          void* stream) {
-    (void)ws;
-    (void)ws_bytes;
     cfsim_status s;
     if ((s = check_graph(A, "A")) != CFSIM_OK) return s;
     if ((s = check_graph(B, "B")) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
     if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
     const int esize = esize_of(opt->dtype);
-    int variant = -1;
     cfsim::PairShape sh;
-    for (int v = 0; v < cfsim::kNumVariants && variant < 0; ++v)
-        if (cfsim::choose_shape(A->n, B->n, A->nnz, B->nnz, v, esize, &sh)) variant = v;
+    const int variant = plain_variant(A->n, B->n, A->nnz, B->nnz, esize, &sh);
     if (variant < 0)
-        return fail(CFSIM_E_UNSUPPORTED, "pair %d x %d does not fit the LDS-resident kernel", B->n, A->n);
+        return fail(CFSIM_E_UNSUPPORTED, "pair %d x %d: its graph lists do not fit the kernels' LDS", B->n, A->n);
+    const size_t need = cfsim_score_workspace_size(ctx, A->n, B->n, opt);
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     cfsim::PairJob job{};
     job.single = 1;
@@ -280,7 +336,8 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     job.match = match_out;
     job.S_out = S_out;
     job.variant = variant;
-    job.lds_bytes = cfsim::variant_info(variant, esize).lds_bytes;
+    job.gws = ws;
+    job.slot_elems = (long long)A->n * B->n;
     int e = (int)hipSetDevice(ctx->device);
     if (e != 0) return hip_fail(e, "hipSetDevice");
     e = cfsim::launch_pair_lds(variant, opt->dtype, job, 1, static_cast<hipStream_t>(stream));
@@ -294,21 +351,23 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
     (void)ctx;
     (void)set;
     (void)opt;
-    if (n_pairs < 0) return 0;
-    return batch_ws_bytes(n_pairs);
+    if (n_pairs < 0 || !set || !opt || set->max_nodes < 1) return 0;
+    return batch_ws_bytes(ctx, n_pairs, esize_of(opt->dtype), set->max_nodes);
 }
 
 static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
                          int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
                          hipStream_t st) {
-    const BatchWs b = carve_batch(ws, n_pairs);
+    const int esize = esize_of(opt->dtype);
+    const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
     cfsim::PlanJob plan;
     plan.set = ref_of(set);
     plan.pair_a = pair_a;
     plan.pair_b = pair_b;
     plan.n_pairs = n_pairs;
-    plan.esize = esize_of(opt->dtype);
+    plan.esize = esize;
+    plan.slot_elems = global_slot_elems(set->max_nodes);
     plan.order = b.order;
     plan.bounds = b.bounds;
     plan.queues = b.queues;
@@ -328,17 +387,30 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
     job.S_out = S_out;
     job.S_off = S_off;
     const int d = dtype_index(opt->dtype);
-    // largest pairs first: bucket V-1 down to 0, then the pairs no bucket holds
-    for (int v = cfsim::kNumVariants - 1; v >= 0; --v) {
-        job.variant = v;
-        job.lds_bytes = cfsim::variant_info(v, esize_of(opt->dtype)).lds_bytes;
+    // Fork: every bucket kernel runs on its own stream after the plan, so the
+    // tail of one bucket overlaps the next; the caller's stream joins them all.
+    if ((e = (int)hipEventRecord(ctx->fork, st)) != 0) return e;
+    for (int v = cfsim::kBucketInvalid; v >= 0; --v) {
+        hipStream_t sv = ctx->side[v];
+        if ((e = (int)hipStreamWaitEvent(sv, ctx->fork, 0)) != 0) return e;
         job.bounds = b.bounds + 2 * v;
         job.queue = b.queues + v;
-        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, ctx->grid[d][v], st)) != 0) return e;
+        job.variant = v;
+        int grid = 1;
+        if (v < cfsim::kNumVariants) {
+            job.gws = b.slots[v];
+            job.slot_elems = cfsim::variant_slot_elems(v, esize);
+            grid = ctx->grid[d][v];
+        } else if (v == cfsim::kBucketGlobal) {
+            job.gws = b.slots[v];
+            job.slot_elems = global_slot_elems(set->max_nodes);
+            grid = ctx->grid[d][v];
+        }
+        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, grid, sv)) != 0) return e;
+        if ((e = (int)hipEventRecord(ctx->join[v], sv)) != 0) return e;
+        if ((e = (int)hipStreamWaitEvent(st, ctx->join[v], 0)) != 0) return e;
     }
-    job.bounds = b.bounds + 2 * cfsim::kNumVariants;
-    job.queue = b.queues + cfsim::kNumVariants;
-    return cfsim::launch_pair_lds(cfsim::kNumVariants, opt->dtype, job, 1, st);
+    return 0;
 }
 
 cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -356,7 +428,8 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
         return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
     if ((S_out == nullptr) != (S_off == nullptr))
         return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
-    const size_t need = batch_ws_bytes(n_pairs);
+    if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
+    const size_t need = batch_ws_bytes(ctx, n_pairs, esize_of(opt->dtype), set->max_nodes);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     if (n_pairs == 0) return ok();

@@ -64,29 +64,26 @@ struct PairShape {
 // Kernel-variant table of the LDS-resident pair kernel.
 struct Variant {
     int nt;         // threads per workgroup
-    int nch;        // max 64-column chunks per lane
-    int maxr;       // max rows per wave (S_{k-2} registers = nch * maxr)
+    int nch;        // max 64-column chunks (lane lists held in VGPRs)
     int lds_bytes;  // dynamic LDS per workgroup
 };
 
-constexpr int kNumVariants = 4;
+constexpr int kNumVariants = 5;
 // Larger variants serve larger pairs; a pair runs on the first that fits.
-// FP64 keeps half as many S_{k-2} values per lane in registers.
 __host__ __device__ inline Variant variant_info(int v, int esize) {
-    if (esize == 8) {
-        switch (v) {
-            case 0: return Variant{64, 1, 16, 16 * 1024};
-            case 1: return Variant{256, 2, 8, 40 * 1024};
-            case 2: return Variant{512, 2, 8, 78 * 1024};
-            default: return Variant{1024, 2, 8, 159 * 1024};
-        }
-    }
     switch (v) {
-        case 0: return Variant{64, 2, 16, 16 * 1024};
-        case 1: return Variant{256, 4, 8, 40 * 1024};
-        case 2: return Variant{512, 2, 16, 78 * 1024};
-        default: return Variant{1024, 4, 8, 159 * 1024};
+        case 0: return Variant{64, esize == 8 ? 1 : 2, 16 * 1024};
+        case 1: return Variant{256, esize == 8 ? 2 : 4, 40 * 1024};
+        case 2: return Variant{512, 2, 78 * 1024};
+        case 3: return Variant{1024, 2, 159 * 1024};
+        default: return Variant{1024, 4, 159 * 1024};
     }
+}
+
+// Elements of the per-workgroup S_{k-2} slot an LDS variant needs (the most
+// entries two S buffers of its LDS budget can hold).
+__host__ __device__ inline long long variant_slot_elems(int v, int esize) {
+    return (long long)variant_info(v, esize).lds_bytes / (2 * esize);
 }
 
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
@@ -101,18 +98,48 @@ __host__ __device__ inline PairShape make_shape(int nA, int nB, int swap, int NW
     return s;
 }
 
-// Bytes of dynamic LDS one pair needs in the LDS-resident kernel.
-// Layout: S_cur, S_next [nR*nC] | R rows int4 [nR] | R succ, pred edges [nnzR]
+// Bytes of one inline R-row record (see RowRec in pair.hip).
+__host__ __device__ inline size_t rowrec_bytes(int esize) { return esize == 8 ? 80 : 48; }
+
+// Bytes of the staged graph lists of one pair (both kernels keep them in LDS).
+// Layout: row records [nR] | row starts int2 [nR] | R succ, pred edges [nnzR]
 //         | C columns int4 [nC] | C succ, pred edges [nnzC]
 //         | rstate, rbest [nR] | cstate, cbest [nC]
-__host__ __device__ inline size_t lds_pair_bytes(const PairShape& s, int nnzR, int nnzC, int esize) {
+__host__ __device__ inline size_t lds_lists_bytes(int nR, int nC, int nnzR, int nnzC, int esize) {
     const size_t edge = (esize == 8) ? 16 : 8;
-    size_t b = 2 * align16((size_t)s.nR * s.nC * esize);
-    b += align16((size_t)s.nR * 16) + 2 * align16((size_t)nnzR * edge);
-    b += align16((size_t)s.nC * 16) + 2 * align16((size_t)nnzC * edge);
-    b += 2 * align16((size_t)s.nR * 4);
-    b += 2 * align16((size_t)s.nC * 4);
+    size_t b = align16((size_t)nR * rowrec_bytes(esize)) + align16((size_t)nR * 8);
+    b += 2 * align16((size_t)nnzR * edge);
+    b += align16((size_t)nC * 16) + 2 * align16((size_t)nnzC * edge);
+    b += 2 * align16((size_t)nR * 4);
+    b += 2 * align16((size_t)nC * 4);
     return b;
+}
+
+// Bytes of dynamic LDS one pair needs in the LDS-resident kernel:
+// S_cur, S_next [nR*nC] followed by the lists.
+__host__ __device__ inline size_t lds_pair_bytes(const PairShape& s, int nnzR, int nnzC, int esize) {
+    return 2 * align16((size_t)s.nR * s.nC * esize) + lds_lists_bytes(s.nR, s.nC, nnzR, nnzC, esize);
+}
+
+// The global-memory kernel: one workgroup per pair, S_cur, S_next and S_{k-2}
+// in a workspace slot of `slot_elems` elements each; lists in LDS.
+constexpr int kGlobalThreads = 512;
+constexpr int kGlobalLds = 78 * 1024;
+
+// Orientation that fills 64-lane chunks better (ties keep S as n_B x n_A).
+__host__ __device__ inline int preferred_swap(int nA, int nB) {
+    const int cA = (nA + 63) / 64, cB = (nB + 63) / 64;
+    return ((long long)nB * cA > (long long)nA * cB) ? 1 : 0;
+}
+
+__host__ __device__ inline bool global_fits(int nA, int nB, int nnzA, int nnzB, int esize, long long slot_elems,
+                                            PairShape* out) {
+    const PairShape s = make_shape(nA, nB, preferred_swap(nA, nB), kGlobalThreads / 64);
+    const int nnzR = s.swap ? nnzA : nnzB, nnzC = s.swap ? nnzB : nnzA;
+    if ((long long)nA * nB > slot_elems) return false;
+    if (lds_lists_bytes(s.nR, s.nC, nnzR, nnzC, esize) > (size_t)kGlobalLds) return false;
+    *out = s;
+    return true;
 }
 
 // Orientation choice: prefer the one that fills 64-lane chunks better; take
@@ -121,14 +148,13 @@ __host__ __device__ inline bool choose_shape(int nA, int nB, int nnzA, int nnzB,
                                              PairShape* out) {
     const Variant v = variant_info(variant, esize);
     const int NW = v.nt / 64;
-    const int cA = (nA + 63) / 64, cB = (nB + 63) / 64;
-    const int pref = ((long long)nB * cA > (long long)nA * cB) ? 1 : 0;
+    const int pref = preferred_swap(nA, nB);
     for (int k = 0; k < 2; ++k) {
         const int swap = k == 0 ? pref : 1 - pref;
         const PairShape s = make_shape(nA, nB, swap, NW);
         const int nnzR = swap ? nnzA : nnzB;
         const int nnzC = swap ? nnzB : nnzA;
-        if (s.nchunk <= v.nch && s.rows <= v.maxr &&
+        if (s.nchunk <= v.nch &&
             lds_pair_bytes(s, nnzR, nnzC, esize) <= (size_t)v.lds_bytes) {
             *out = s;
             return true;
@@ -160,27 +186,39 @@ struct PairJob {
     const int64_t* S_off;
     int variant;
     int lds_bytes;
+    // Workspace of gridDim.x slots of slot_elems elements each: S_{k-2} (LDS
+    // kernel), or S_cur, S_next, S_{k-2} at 3 * slot_elems (global kernel).
+    void* gws;
+    long long slot_elems;
 };
 
-// Plan: assign every pair a variant (bucket) and order each bucket longest
-// first.  Writes order[n_pairs], bounds[2*(kNumVariants+1)] and zeroes the
-// queues[kNumVariants+1].  Bucket kNumVariants holds pairs no variant fits.
+// Plan: assign every pair a bucket and order each bucket longest first.
+// Buckets 0..kNumVariants-1 are the LDS variants, kNumVariants the
+// global-memory kernel, kNumVariants+1 the pairs no kernel can take (bad
+// graph ids, empty graphs, lists too long for LDS).  Writes order[n_pairs],
+// bounds[2*kBuckets] and zeroes queues[kBuckets].
+constexpr int kBucketGlobal = kNumVariants;
+constexpr int kBucketInvalid = kNumVariants + 1;
+constexpr int kBuckets = kNumVariants + 2;
 struct PlanJob {
     SetRef set;
     const int32_t* pair_a;
     const int32_t* pair_b;
     int64_t n_pairs;
     int esize;
+    long long slot_elems;
     int32_t* order;
     int32_t* bounds;
     int32_t* queues;
 };
 
 // Host-side launchers (return hipError_t as int).
+// variant in [0, kNumVariants): LDS kernel; kBucketGlobal: global-memory
+// kernel; kBucketInvalid: marks the bucket's pairs invalid.
 int launch_pair_lds(int variant, int dtype, const PairJob& job, int grid, hipStream_t stream);
 int launch_plan(const PlanJob& job, hipStream_t stream);
 int set_kernel_attributes();
-int occupancy_of(int variant, int dtype, int* blocks);
+int occupancy_of(int variant, int dtype, int* blocks);  // variant may be kBucketGlobal
 
 struct PackJob {
     int n_graphs;

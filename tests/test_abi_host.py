@@ -37,10 +37,10 @@ def _graph(n=3, nnz=2):
     return cf.Graph(n, nnz, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000)
 
 
-def _call_score(A, B, opt, res=0x1000):
+def _call_score(A, B, opt, res=0x1000, ws=0x1000, ws_bytes=1 << 30):
     L = cf.lib()
     return L.cfsim_score(None, ctypes.byref(A) if A is not None else None, ctypes.byref(B) if B is not None else None,
-                         ctypes.byref(opt) if opt is not None else None, None, None, res, None, 0, None)
+                         ctypes.byref(opt) if opt is not None else None, None, None, res, ws, ws_bytes, None)
 
 
 @pytest.mark.parametrize("case,code,text", [
@@ -57,6 +57,7 @@ def _call_score(A, B, opt, res=0x1000):
     ("null_graph", -1, "NULL"),
     ("null_res", -1, "res"),
     ("null_ctx", -1, "context"),
+    ("small_ws", -5, "workspace"),
 ])
 def test_score_validation(case, code, text):
     A, B = _graph(), _graph(4, 3)
@@ -86,15 +87,23 @@ def test_score_validation(case, code, text):
         A = None
     elif case == "null_res":
         res = None
-    got = _call_score(A, B, opt, res)
+    ws_bytes = 16 if case == "small_ws" else 1 << 30
+    got = _call_score(A, B, opt, res, ws_bytes=ws_bytes)
     assert got == code
     assert text in cf.lib().cfsim_last_error().decode()
+
+
+def test_score_workspace_size():
+    L = cf.lib()
+    opt = cf.options("f32")
+    assert L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >= 3 * 12 * 16 * 4
+    assert L.cfsim_score_workspace_size(None, 0, 16, ctypes.byref(opt)) == 0
 
 
 def test_score_too_large_pair_is_unsupported():
     A, B = _graph(3000, 4000), _graph(3000, 4000)
     assert _call_score(A, B, cf.options("f32")) == -6
-    assert "does not fit" in cf.lib().cfsim_last_error().decode()
+    assert "do not fit" in cf.lib().cfsim_last_error().decode()
 
 
 def _set(**kw):
