@@ -121,7 +121,7 @@ def _set(**kw):
     (dict(w=None), 5, 1 << 20, -1, "edge array"),
     ({}, -1, 1 << 20, -1, "n_pairs"),
     ({}, 5, 16, -5, "workspace"),
-    ({}, 5, 1 << 20, -1, "context"),
+    ({}, 5, 1 << 40, -1, "context"),
 ])
 def test_batch_validation(kw, n_pairs, ws, code, text):
     L = cf.lib()
