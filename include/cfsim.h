@@ -182,6 +182,40 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
                                void* S_out, const int64_t* S_off,
                                void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Step a10 - reverse mode: d(sum_p grad_score[p] * score_p) / d(w), added to
+ * grad_w[total_edges] (device, FP64, CSR order of `set`; not cleared).  The
+ * matching and the update count of each pair are held fixed (the
+ * almost-everywhere derivative): fwd[p].iters and match (at match_off[p])
+ * must come from the forward call with the same set, pairs and options.
+ * The forward is recomputed with S stored every checkpoint_every updates.
+ * Degenerate pairs contribute zero.  pair_status[n_pairs] (device, may be
+ * NULL) receives 0, or CFSIM_INVALID_INPUT for a pair that was skipped (bad
+ * ids, or lists too long for the kernel).  Graphs shared between pairs
+ * accumulate with FP64 atomics (summation order not fixed).  ws is a device
+ * workspace of cfsim_backward_workspace_size() bytes.
+ */
+size_t cfsim_backward_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
+                                     const cfsim_options* opt, int32_t checkpoint_every);
+cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                  const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                                  const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
+                                  const double* grad_score, double* grad_w, int32_t* pair_status,
+                                  int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Step a11 - ranking of a query against a database: the k best scores.
+ * scores[i * stride] for i in [0, n) (device; stride 4 reads the score field
+ * of a cfsim_pair_result array).  Larger score first, ties to the lower
+ * index, NaN (invalid pairs) ranks as -infinity.  idx_out[k] and score_out[k]
+ * (device) receive the indices and scores; entries past n get index -1 and
+ * score -infinity.  1 <= k <= 1024; ws is a device workspace of
+ * cfsim_topk_workspace_size(n, k) bytes.
+ */
+size_t cfsim_topk_workspace_size(int64_t n, int32_t k);
+cfsim_status cfsim_topk(cfsim_context* ctx, const double* scores, int64_t n, int64_t stride, int32_t k,
+                        int32_t* idx_out, double* score_out, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

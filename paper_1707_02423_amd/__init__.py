@@ -5,5 +5,5 @@ include/cfsim.h); `cfsim.py` is the thin ctypes binding.
 """
 from .cfsim import (  # noqa: F401
     F32, F64, CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, RESULT_DTYPE,
-    Batch, CfsimError, Context, GraphSet, lib, options, pack, score, score_batch,
+    Batch, CfsimError, CfsimScore, Context, GraphSet, backward, lib, options, pack, score, score_batch, topk,
 )

@@ -73,6 +73,11 @@ SIGNATURES = {
     "cfsim_batch_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options)]),
     "cfsim_score_batch": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
                                          _P, _P, _P, _P, _P, _SZ, _P]),
+    "cfsim_backward_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options), _I32]),
+    "cfsim_score_backward": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
+                                            _P, _P, _P, _P, _P, _P, _I32, _P, _SZ, _P]),
+    "cfsim_topk_workspace_size": (_SZ, [_I64, _I32]),
+    "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
 }
 
 
@@ -307,6 +312,11 @@ class Batch:
                                        _ptr(self.match), _ptr(self.match_off), _ptr(self.S), _ptr(self.S_off),
                                        _ptr(self.ws), self.ws_bytes, _stream(stream)))
 
+    def topk(self, k: int, stream=None):
+        """Top-k of this batch's scores, on the device (call after run())."""
+        scores = self.res[: self.n_pairs * 32].view(torch.float64)
+        return topk(self.ctx, scores, k, stride=4, n=self.n_pairs, stream=stream)
+
     def results(self) -> np.ndarray:
         return self.res[: self.n_pairs * 32].cpu().numpy().view(RESULT_DTYPE)
 
@@ -317,6 +327,67 @@ class Batch:
     def S_list(self):
         S = self.S.cpu().numpy()
         return [S[o:o + a * b].reshape(b, a) for o, a, b in zip(self.S_off_h, self.nA, self.nB)]
+
+
+def topk(ctx: Context, scores: torch.Tensor, k: int, stride: int = 1, n: int | None = None, stream=None):
+    """Step a11 on the device: indices and values of the k best scores
+    (ties to the lower index, NaN ranks last).  `scores` is a float64 device
+    tensor read with `stride` (4 reads the score field of a result array)."""
+    n = int(scores.numel() // stride) if n is None else int(n)
+    dev = scores.device
+    idx = torch.empty(k, dtype=torch.int32, device=dev)
+    val = torch.empty(k, dtype=torch.float64, device=dev)
+    ws_bytes = lib().cfsim_topk_workspace_size(n, k)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().cfsim_topk(ctx.handle, _ptr(scores), n, stride, k, _ptr(idx), _ptr(val), _ptr(ws), ws_bytes,
+                            _stream(stream)))
+    return idx, val
+
+
+def backward(batch: "Batch", grad_score: torch.Tensor, grad_w: torch.Tensor, checkpoint_every: int = 8,
+             stream=None) -> torch.Tensor:
+    """Step a10: adds d(sum_p grad_score[p] score_p)/dw to grad_w (FP64, CSR
+    order of the set) for the pairs of a batch that has run.  Returns the
+    per-pair status (0, or INVALID_INPUT for skipped pairs)."""
+    if batch.match is None:
+        raise ValueError("the backward needs the forward's matchings: build the Batch with want_match=True")
+    dev = batch.gs.w.device
+    gsc = grad_score.to(device=dev, dtype=torch.float64).contiguous()
+    status = torch.empty(max(batch.n_pairs, 1), dtype=torch.int32, device=dev)
+    L = lib()
+    ws_bytes = L.cfsim_backward_workspace_size(batch.ctx.handle, ctypes.byref(batch.set_c), batch.n_pairs,
+                                               ctypes.byref(batch.opt), int(checkpoint_every))
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(L.cfsim_score_backward(batch.ctx.handle, ctypes.byref(batch.set_c), _ptr(batch.pair_a),
+                                  _ptr(batch.pair_b), batch.n_pairs, ctypes.byref(batch.opt), _ptr(batch.res),
+                                  _ptr(batch.match), _ptr(batch.match_off), _ptr(gsc), _ptr(grad_w), _ptr(status),
+                                  int(checkpoint_every), _ptr(ws), ws_bytes, _stream(stream)))
+    return status[: batch.n_pairs]
+
+
+class CfsimScore(torch.autograd.Function):
+    """scores = CfsimScore.apply(w, ctx, gs, pair_a, pair_b, dtype, max_iter, tol, checkpoint_every)
+
+    w is the packed edge-weight tensor (FP64, CSR order of `gs`, e.g. gs.w or
+    a tensor computed from counts with torch); the result is the FP64 score of
+    every pair.  backward returns d(loss)/dw through the hand-written adjoint
+    kernel (matching and update count held fixed)."""
+
+    @staticmethod
+    def forward(ctx_, w, cfctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, checkpoint_every=8):
+        w = w.detach().contiguous()
+        b = Batch(cfctx, gs, pair_a, pair_b, dtype=dtype, max_iter=max_iter, tol=tol, want_match=True, w=w)
+        b.run()
+        ctx_.batch = b
+        ctx_.w = w
+        ctx_.checkpoint_every = checkpoint_every
+        return b.res[: b.n_pairs * 32].view(torch.float64)[0::4].clone()
+
+    @staticmethod
+    def backward(ctx_, grad_scores):
+        grad_w = torch.zeros_like(ctx_.w, dtype=torch.float64)
+        backward(ctx_.batch, grad_scores, grad_w, ctx_.checkpoint_every)
+        return grad_w, None, None, None, None, None, None, None, None
 
 
 def score_batch(ctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, resize="none", want_match=True,

@@ -490,4 +490,67 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
     return ok();
 }
 
+// ------------------------------------------------------------------ adjoint (a10)
+size_t cfsim_backward_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
+                                     const cfsim_options* opt, int32_t checkpoint_every) {
+    (void)n_pairs;
+    if (!set || !opt || set->max_nodes < 1 || checkpoint_every < 1 || opt->max_iter < 1) return 0;
+    const long long slot = global_slot_elems(set->max_nodes);
+    return 256 + (size_t)cfsim::backward_grid(num_cus_of(ctx)) *
+                     (size_t)cfsim::backward_slot_bytes(opt->max_iter, checkpoint_every, slot, esize_of(opt->dtype));
+}
+
+cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                  const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                                  const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
+                                  const double* grad_score, double* grad_w, int32_t* pair_status,
+                                  int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream) {
+    cfsim_status s;
+    if ((s = check_set(set)) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
+    if (checkpoint_every < 1) return fail(CFSIM_E_INVALID_ARG, "checkpoint_every must be >= 1");
+    if (n_pairs > 0 && (!pair_a || !pair_b || !fwd || !match || !match_off || !grad_score || !grad_w))
+        return fail(CFSIM_E_INVALID_ARG, "a pair, forward-result, matching or gradient array is NULL");
+    if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
+    const size_t need = cfsim_backward_workspace_size(ctx, set, n_pairs, opt, checkpoint_every);
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_pairs == 0) return ok();
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    e = cfsim::launch_backward(opt->dtype, ref_of(set), pair_a, pair_b, (int)n_pairs, fwd, match, match_off,
+                               grad_score, grad_w, pair_status, checkpoint_every, opt->max_iter, ws,
+                               global_slot_elems(set->max_nodes), cfsim::backward_grid(ctx->num_cus),
+                               static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "backward launch");
+    return ok();
+}
+
+// ------------------------------------------------------------------ top-k (a11)
+size_t cfsim_topk_workspace_size(int64_t n, int32_t k) {
+    if (n < 1 || k < 1) return 0;
+    return align256((size_t)cfsim::topk_blocks(n) * (size_t)k * 16);
+}
+
+cfsim_status cfsim_topk(cfsim_context* ctx, const double* scores, int64_t n, int64_t stride, int32_t k,
+                        int32_t* idx_out, double* score_out, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1) return fail(CFSIM_E_INVALID_ARG, "n must be >= 1");
+    if (n > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 scores");
+    if (stride < 1) return fail(CFSIM_E_INVALID_ARG, "stride must be >= 1");
+    if (k < 1 || k > cfsim::topk_max_k()) return fail(CFSIM_E_INVALID_ARG, "k must be in [1, %d]", cfsim::topk_max_k());
+    if (!scores || !idx_out || !score_out) return fail(CFSIM_E_INVALID_ARG, "scores, idx_out or score_out is NULL");
+    if (cfsim::topk_stage2_lds(n, k) > 159 * 1024)
+        return fail(CFSIM_E_UNSUPPORTED, "n * k too large for the two-stage selection");
+    const size_t need = cfsim_topk_workspace_size(n, k);
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    e = cfsim::launch_topk(scores, n, stride, k, idx_out, score_out, ws, static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "top-k launch");
+    return ok();
+}
+
 }  // extern "C"

@@ -240,4 +240,19 @@ struct PackJob {
 };
 int launch_pack(const PackJob& job, hipStream_t stream);
 
+// Adjoint (adjoint.hip).
+long long backward_slot_bytes(int max_iter, int ckpt, long long slot_elems, int esize);
+int backward_grid(int num_cus);
+int launch_backward(int dtype, const SetRef& set, const int32_t* pair_a, const int32_t* pair_b, int n_pairs,
+                    const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
+                    const double* grad_score, double* grad_w, int32_t* pair_status, int ckpt, int max_iter,
+                    void* ws, long long slot_elems, int grid, hipStream_t stream);
+
+// Top-k (topk.hip).
+long long topk_blocks(long long n);
+int topk_max_k();
+size_t topk_stage2_lds(long long n, int k);
+int launch_topk(const double* scores, long long n, long long stride, int k, int32_t* idx_out, double* score_out,
+                void* ws, hipStream_t stream);
+
 }  // namespace cfsim

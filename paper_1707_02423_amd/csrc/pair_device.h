@@ -1,0 +1,401 @@
+// Device building blocks shared by the forward (pair.hip) and adjoint
+// (adjoint.hip) kernels: edge and row records, per-lane neighbour lists, the
+// update of one row of Y = B S A^T + B^T S A, staging of a pair's lists into
+// LDS, and fixed-order reductions.
+#pragma once
+
+#include <float.h>
+#include <limits.h>
+
+#include "cfsim_internal.h"
+
+namespace cfsim {
+namespace dev {
+
+constexpr int kDS = 2;  // successors per lane column held in VGPRs
+constexpr int kDP = 3;  // predecessors per lane column held in VGPRs
+
+template <typename T>
+struct alignas(sizeof(T) == 8 ? 16 : 8) Edge {
+    int32_t u;
+    T w;
+};
+
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline float uni(float x) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+__device__ inline double uni(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+__device__ inline double wave_sum(double x) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+    return x;
+}
+__device__ inline int wave_max(int x) {
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
+    return x;
+}
+template <typename T>
+__device__ inline bool better(T v, int k, T bv, int bk) {
+    return v > bv || (v == bv && k < bk);
+}
+template <typename T>
+__device__ inline void wave_argmax(T& v, int& k, int& c) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(v, o, kWave);
+        const int ok = __shfl_xor(k, o, kWave);
+        const int oc = __shfl_xor(c, o, kWave);
+        if (better(ov, ok, v, k)) {
+            v = ov;
+            k = ok;
+            c = oc;
+        }
+    }
+}
+
+// Neighbour lists of the lane's column in one 64-column chunk, padded with
+// zero weights: the first kDS successors and kDP predecessors as byte offsets
+// into a row of S.  Longer lists are finished by the overflow pass.
+template <typename T>
+struct LaneList {
+    int sv[kDS];
+    T sw[kDS];
+    int pv[kDP];
+    T pw[kDP];
+};
+
+// Inline record of one R row, read with one broadcast: the first kDS
+// successors and kDP predecessors as byte offsets of S rows, their weights,
+// and the list lengths (padding has zero weight).
+template <typename T>
+struct alignas(16) RowRec {
+    int ns, np;
+    int su[kDS];
+    int pu[kDP];
+    T sw[kDS];
+    T pw[kDP];
+};
+
+template <typename T>
+__device__ inline T lds_at(const unsigned char* base, int byte_off) {
+    return *reinterpret_cast<const T*>(base + byte_off);
+}
+
+template <typename T>
+__device__ inline void load_lane(const int4* cinfo, const Edge<T>* cse, const Edge<T>* cpe, int c, bool valid,
+                                 LaneList<T>& L) {
+    const int esz = (int)sizeof(T);
+    const int4 ci = cinfo[valid ? c : 0];
+    const int sdeg = valid ? ci.y - ci.x : 0;
+    const int pdeg = valid ? ci.w - ci.z : 0;
+#pragma unroll
+    for (int q = 0; q < kDS; ++q) {
+        const bool has = q < sdeg;
+        const Edge<T> e = cse[has ? ci.x + q : 0];
+        L.sv[q] = has ? e.u * esz : 0;
+        L.sw[q] = has ? e.w : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kDP; ++q) {
+        const bool has = q < pdeg;
+        const Edge<T> e = cpe[has ? ci.z + q : 0];
+        L.pv[q] = has ? e.u * esz : 0;
+        L.pw[q] = has ? e.w : T(0);
+    }
+}
+
+// One R-side term: y + w * sum_q wl[q] S[u][v_q]  (row u at byte offset uo).
+template <typename T, int D>
+__device__ inline T lane_term(const unsigned char* Sb, int uo, T w, const int (&v)[D], const T (&wl)[D], T y) {
+    T a = wl[0] * lds_at<T>(Sb, uo + v[0]);
+#pragma unroll
+    for (int q = 1; q < D; ++q) a = fma_t(wl[q], lds_at<T>(Sb, uo + v[q]), a);
+    return fma_t(w, a, y);
+}
+
+// Row update specialised on the row's successor / predecessor counts: every
+// S read of the row (all chunks) is independent of the others.
+template <typename T, int NCH, int NS, int NP>
+__device__ inline void row_fixed(const unsigned char* Sb, const int (&su)[kDS], const T (&sw)[kDS],
+                                 const int (&pu)[kDP], const T (&pw)[kDP], const LaneList<T> (&L)[NCH],
+                                 T (&y)[NCH]) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
+#pragma unroll
+    for (int a = 0; a < NS; ++a)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDS>(Sb, su[a], sw[a], L[ch].sv, L[ch].sw, y[ch]);
+#pragma unroll
+    for (int b = 0; b < NP; ++b)
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDP>(Sb, pu[b], pw[b], L[ch].pv, L[ch].pw, y[ch]);
+}
+
+// Rows with longer lists: loops over the staged R edges.
+template <typename T, int NCH>
+__device__ inline void row_loop(const unsigned char* Sb, int rowb, const Edge<T>* se, int ns, const Edge<T>* pe,
+                                int np, const LaneList<T> (&L)[NCH], T (&y)[NCH]) {
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
+    for (int a = 0; a < ns; ++a) {
+        const Edge<T> e = se[a];
+        const int uo = uni(e.u) * rowb;
+        const T w = uni(e.w);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDS>(Sb, uo, w, L[ch].sv, L[ch].sw, y[ch]);
+    }
+    for (int b = 0; b < np; ++b) {
+        const Edge<T> e = pe[b];
+        const int uo = uni(e.u) * rowb;
+        const T w = uni(e.w);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDP>(Sb, uo, w, L[ch].pv, L[ch].pw, y[ch]);
+    }
+}
+
+// Lane-list entries past the padded kDS / kDP of column c (long C lists).
+template <typename T>
+__device__ inline T row_overflow(const unsigned char* Sb, int rowb, const Edge<T>* se, int ns, const Edge<T>* pe,
+                                 int np, const int4* cinfo, const Edge<T>* cse, const Edge<T>* cpe, int c,
+                                 bool valid) {
+    const int esz = (int)sizeof(T);
+    const int4 ci = cinfo[valid ? c : 0];
+    const int sdeg = valid ? ci.y - ci.x : 0;
+    const int pdeg = valid ? ci.w - ci.z : 0;
+    T y = T(0);
+    for (int a = 0; a < ns; ++a) {
+        const Edge<T> e = se[a];
+        const int uo = uni(e.u) * rowb;
+        T acc = T(0);
+        for (int q = kDS; q < sdeg; ++q) {
+            const Edge<T> x = cse[ci.x + q];
+            acc = fma_t(x.w, lds_at<T>(Sb, uo + x.u * esz), acc);
+        }
+        y = fma_t(uni(e.w), acc, y);
+    }
+    for (int b = 0; b < np; ++b) {
+        const Edge<T> e = pe[b];
+        const int uo = uni(e.u) * rowb;
+        T acc = T(0);
+        for (int q = kDP; q < pdeg; ++q) {
+            const Edge<T> x = cpe[ci.z + q];
+            acc = fma_t(x.w, lds_at<T>(Sb, uo + x.u * esz), acc);
+        }
+        y = fma_t(uni(e.w), acc, y);
+    }
+    return y;
+}
+
+__device__ inline void write_invalid(cfsim_pair_result* r) {
+    r->score = __builtin_nan("");
+    r->nu = 0.0;
+    r->delta = __builtin_inf();
+    r->iters = 0;
+    r->status = CFSIM_INVALID_INPUT;
+}
+
+struct IterOut {
+    double nu, delta;
+    int iters;
+    unsigned status;
+    int final_buf;  // 0: S in the first buffer, 1: in the second
+};
+
+// ---------------------------------------------------------------- per-pair pieces
+// Graphs, orientation and result slot of pair p.
+struct PairHdr {
+    GraphRef A, B, R, C;
+    PairShape sh;
+    cfsim_pair_result* res;
+};
+
+// Resolves the graphs of pair p; false (and an INVALID result) if unusable.
+__device__ inline bool resolve_graphs(const PairJob& J, int p, GraphRef& A, GraphRef& B, cfsim_pair_result*& res) {
+    res = J.res + (J.single ? 0 : p);
+    if (J.single) {
+        A = J.ga;
+        B = J.gb;
+    } else {
+        const int ga = J.pair_a[p], gb = J.pair_b[p];
+        if (ga < 0 || ga >= J.set.n_graphs || gb < 0 || gb >= J.set.n_graphs) return false;
+        A = graph_of(J.set, ga);
+        B = graph_of(J.set, gb);
+    }
+    return A.n >= 1 && B.n >= 1;
+}
+
+// Staged graph lists of one pair in LDS (layout of lds_lists_bytes).
+template <typename T>
+struct Lists {
+    RowRec<T>* rec;
+    int2* rstart;
+    Edge<T>* sedge;
+    Edge<T>* pedge;
+    int4* cinfo;
+    Edge<T>* csedge;
+    Edge<T>* cpedge;
+    int *rstate, *rbest, *cstate, *cbest;
+};
+
+template <typename T>
+__device__ inline Lists<T> carve_lists(unsigned char* base, int nR, int nC, int nnzR, int nnzC) {
+    Lists<T> L;
+    size_t off = 0;
+    L.rec = reinterpret_cast<RowRec<T>*>(base + off);
+    off += align16((size_t)nR * sizeof(RowRec<T>));
+    L.rstart = reinterpret_cast<int2*>(base + off);
+    off += align16((size_t)nR * 8);
+    L.sedge = reinterpret_cast<Edge<T>*>(base + off);
+    off += align16((size_t)nnzR * sizeof(Edge<T>));
+    L.pedge = reinterpret_cast<Edge<T>*>(base + off);
+    off += align16((size_t)nnzR * sizeof(Edge<T>));
+    L.cinfo = reinterpret_cast<int4*>(base + off);
+    off += align16((size_t)nC * 16);
+    L.csedge = reinterpret_cast<Edge<T>*>(base + off);
+    off += align16((size_t)nnzC * sizeof(Edge<T>));
+    L.cpedge = reinterpret_cast<Edge<T>*>(base + off);
+    off += align16((size_t)nnzC * sizeof(Edge<T>));
+    L.rstate = reinterpret_cast<int*>(base + off);
+    off += align16((size_t)nR * 4);
+    L.rbest = reinterpret_cast<int*>(base + off);
+    off += align16((size_t)nR * 4);
+    L.cstate = reinterpret_cast<int*>(base + off);
+    off += align16((size_t)nC * 4);
+    L.cbest = reinterpret_cast<int*>(base + off);
+    return L;
+}
+
+// Stages the R rows (inline records) and both edge lists, writes S_0 into S,
+// and returns whether the pair is degenerate (a graph without positive weight).
+template <typename T, int NT>
+__device__ bool stage_pair(const GraphRef& R, const GraphRef& C, int nR, int nC, const Lists<T>& L, T* S, T s0) {
+    const int tid = threadIdx.x;
+    const int rowb = nC * (int)sizeof(T);
+    static_assert(sizeof(RowRec<T>) == (sizeof(T) == 8 ? 80 : 48), "row record size");
+    for (int r = tid; r < nR; r += NT) {
+        const int sb = R.rp[r], se = R.rp[r + 1], pb = R.cp[r], pe = R.cp[r + 1];
+        RowRec<T> x;
+        x.ns = se - sb;
+        x.np = pe - pb;
+#pragma unroll
+        for (int q = 0; q < kDS; ++q) {
+            const bool has = q < x.ns;
+            x.su[q] = has ? R.ci[sb + q] * rowb : 0;
+            x.sw[q] = has ? T(R.w[sb + q]) : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < kDP; ++q) {
+            const bool has = q < x.np;
+            x.pu[q] = has ? R.ri[pb + q] * rowb : 0;
+            x.pw[q] = has ? T(R.w[R.eid[pb + q]]) : T(0);
+        }
+        L.rec[r] = x;
+        L.rstart[r] = make_int2(sb, pb);
+    }
+    for (int c = tid; c < nC; c += NT) L.cinfo[c] = make_int4(C.rp[c], C.rp[c + 1], C.cp[c], C.cp[c + 1]);
+    int posR = 0, posC = 0;
+    for (int t = tid; t < R.nnz; t += NT) {
+        const double w = R.w[t];
+        L.sedge[t].u = R.ci[t];
+        L.sedge[t].w = T(w);
+        L.pedge[t].u = R.ri[t];
+        L.pedge[t].w = T(R.w[R.eid[t]]);
+        posR |= (w > 0.0);
+    }
+    for (int t = tid; t < C.nnz; t += NT) {
+        const double w = C.w[t];
+        L.csedge[t].u = C.ci[t];
+        L.csedge[t].w = T(w);
+        L.cpedge[t].u = C.ri[t];
+        L.cpedge[t].w = T(C.w[C.eid[t]]);
+        posC |= (w > 0.0);
+    }
+    const long long total = (long long)nR * nC;
+    for (long long t = tid; t < total; t += NT) S[t] = s0;
+    const int anyR = __syncthreads_or(posR);
+    const int anyC = __syncthreads_or(posC);
+    return !(anyR && anyC);
+}
+
+// One wave's update of row i: y[ch] for its NCH chunks (all S reads of the row
+// issued together), plus the overflow of long lane lists.
+template <typename T, int NCH>
+__device__ inline void update_row(const unsigned char* Sb, int rowb, int i, const RowRec<T>& rr, const Lists<T>& G,
+                                  const LaneList<T> (&L)[NCH], const bool (&ovf)[NCH], bool any_ovf,
+                                  const int (&col)[NCH], const bool (&cv)[NCH], T (&y)[NCH]) {
+    const int ns = uni(rr.ns), np = uni(rr.np);
+    int su[kDS], pu[kDP];
+    T sw[kDS], pw[kDP];
+#pragma unroll
+    for (int q = 0; q < kDS; ++q) {
+        su[q] = uni(rr.su[q]);
+        sw[q] = uni(rr.sw[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kDP; ++q) {
+        pu[q] = uni(rr.pu[q]);
+        pw[q] = uni(rr.pw[q]);
+    }
+    switch (ns <= 2 && np <= 2 ? ns * 3 + np : -1) {
+        case 0:
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
+            break;
+        case 1: row_fixed<T, NCH, 0, 1>(Sb, su, sw, pu, pw, L, y); break;
+        case 2: row_fixed<T, NCH, 0, 2>(Sb, su, sw, pu, pw, L, y); break;
+        case 3: row_fixed<T, NCH, 1, 0>(Sb, su, sw, pu, pw, L, y); break;
+        case 4: row_fixed<T, NCH, 1, 1>(Sb, su, sw, pu, pw, L, y); break;
+        case 5: row_fixed<T, NCH, 1, 2>(Sb, su, sw, pu, pw, L, y); break;
+        case 6: row_fixed<T, NCH, 2, 0>(Sb, su, sw, pu, pw, L, y); break;
+        case 7: row_fixed<T, NCH, 2, 1>(Sb, su, sw, pu, pw, L, y); break;
+        case 8: row_fixed<T, NCH, 2, 2>(Sb, su, sw, pu, pw, L, y); break;
+        default: {
+            const int2 st = G.rstart[i];
+            row_loop<T, NCH>(Sb, rowb, G.sedge + uni(st.x), ns, G.pedge + uni(st.y), np, L, y);
+            break;
+        }
+    }
+    if (any_ovf) {
+        const int2 st = G.rstart[i];
+        const Edge<T>* se = G.sedge + uni(st.x);
+        const Edge<T>* pe = G.pedge + uni(st.y);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            if (ovf[ch]) y[ch] += row_overflow<T>(Sb, rowb, se, ns, pe, np, G.cinfo, G.csedge, G.cpedge, col[ch], cv[ch]);
+    }
+}
+
+template <typename T>
+__device__ inline void lane_setup(const Lists<T>& G, int ch, int nC, LaneList<T>& L, int& col, bool& cv, bool& ovf) {
+    const int c = ch * kWave + (int)(threadIdx.x & (kWave - 1));
+    cv = c < nC;
+    col = cv ? c : 0;
+    load_lane(G.cinfo, G.csedge, G.cpedge, c, cv, L);
+    const int4 ci = G.cinfo[col];
+    const int extra = cv ? max(ci.y - ci.x - kDS, ci.w - ci.z - kDP) : 0;
+    ovf = uni(wave_max(extra)) > 0;
+}
+
+// Reduces a per-wave double over the workgroup in a fixed order (every
+// thread gets the same value); `red` has NW slots; one barrier.
+template <int NW>
+__device__ inline double block_sum(double x, double* red) {
+    x = wave_sum(x);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < NW; ++w) t += red[w];
+    return t;
+}
+
+
+}  // namespace dev
+}  // namespace cfsim

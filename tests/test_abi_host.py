@@ -164,3 +164,16 @@ def test_pack_validation():
 
 def test_context_create_rejects_null_out():
     assert cf.lib().cfsim_context_create(None, 0) == -1
+
+
+def test_topk_validation():
+    L = cf.lib()
+    P = 0x1000
+    assert L.cfsim_topk(None, P, 0, 1, 4, P, P, P, 1 << 20, None) == -1
+    assert L.cfsim_topk(None, P, 10, 0, 4, P, P, P, 1 << 20, None) == -1
+    assert L.cfsim_topk(None, P, 10, 1, 0, P, P, P, 1 << 20, None) == -1
+    assert L.cfsim_topk(None, P, 10, 1, 2000, P, P, P, 1 << 20, None) == -1
+    assert L.cfsim_topk(None, P, 10, 1, 4, P, P, P, 1, None) == -5
+    assert L.cfsim_topk(None, P, 10, 1, 4, P, P, P, 1 << 20, None) == -1
+    assert "context" in L.cfsim_last_error().decode()
+    assert L.cfsim_topk_workspace_size(65536, 16) >= 16 * 16 * 16

@@ -1,0 +1,129 @@
+"""Adjoint kernel (through the C ABI) against the oracle's reverse mode and
+against central finite differences of the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from cfgsynth import Grammar, config_graphs, make_cfg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_02423_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(cf):
+    return cf.Context(0)
+
+
+def _oracle_edge_grads(graphs, pa, pb, K_list, matches, gscore):
+    """Oracle reverse mode, accumulated into a per-edge vector in pack order."""
+    from paper_1707_02423_amd.cfsim import concat_coo
+    node_off, edge_off, src, dst, cnt = concat_coo(graphs)
+    out = np.zeros(int(edge_off[-1]))
+    for p in range(len(pa)):
+        ga, gb = graphs[pa[p]], graphs[pb[p]]
+        A = oracle.transition_matrix(ga.n, ga.src, ga.dst, ga.count)
+        B = oracle.transition_matrix(gb.n, gb.src, gb.dst, gb.count)
+        dA, dB = oracle.backward(A, B, int(K_list[p]), matches[p])
+        out[edge_off[pa[p]]:edge_off[pa[p] + 1]] += gscore[p] * oracle.edge_gradients(dA, ga.src, ga.dst)
+        out[edge_off[pb[p]]:edge_off[pb[p] + 1]] += gscore[p] * oracle.edge_gradients(dB, gb.src, gb.dst)
+    return out, edge_off
+
+
+def _to_input_order(cf, gs, g_csr, graphs):
+    """Map CSR-order gradients of the packed set back to each graph's input edge order."""
+    out = np.zeros_like(g_csr)
+    for g, G in enumerate(graphs):
+        rp, col, _ = gs.host_csr(g)
+        e0 = int(gs.edge_off[g])
+        # input edge e sits at the CSR position of (src, dst) in input order among equal keys
+        order = np.lexsort((np.arange(G.nnz), G.dst, G.src))
+        out[e0 + order] = g_csr[e0:e0 + G.nnz]
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 2e-4)])
+def test_backward_matches_oracle_reverse_mode(cf, ctx, dtype, tol):
+    rng = np.random.default_rng(17)
+    sizes = [5, 9, 12, 16, 23, 31, 40]
+    graphs = [make_cfg(n, Grammar(counts="trip"), rng) for n in sizes]
+    pa = np.array([0, 1, 2, 3, 4, 5, 6, 2, 3], np.int32)
+    pb = np.array([1, 2, 3, 4, 5, 6, 0, 2, 6], np.int32)     # includes a self pair (2, 2)
+    gs = cf.pack(ctx, graphs)
+    b = cf.Batch(ctx, gs, pa, pb, dtype=dtype, max_iter=60, tol=0.0, want_match=True)
+    b.run()
+    torch.cuda.synchronize()
+    res = b.results()
+    gsc = np.linspace(0.5, 1.5, len(pa))
+    grad_w = torch.zeros(gs.total_edges, dtype=torch.float64, device="cuda")
+    st = cf.backward(b, torch.as_tensor(gsc), grad_w, checkpoint_every=8)
+    torch.cuda.synchronize()
+    assert np.all(st.cpu().numpy() == 0)
+    got = _to_input_order(cf, gs, grad_w.cpu().numpy(), graphs)
+    ref, _ = _oracle_edge_grads(graphs, pa, pb, res["iters"], b.matches(), gsc)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= tol * scale, np.abs(got - ref).max() / scale
+
+
+def test_backward_checkpoint_spacing_does_not_change_result(cf, ctx):
+    w = config_graphs(3, scale=6 / 1024)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", max_iter=37, tol=0.0, want_match=True)
+    b.run()
+    outs = []
+    for c in (1, 5, 8, 40):
+        g = torch.zeros(gs.total_edges, dtype=torch.float64, device="cuda")
+        cf.backward(b, torch.ones(len(w["pair_a"]), dtype=torch.float64), g, checkpoint_every=c)
+        outs.append(g.cpu().numpy())
+    for o in outs[1:]:
+        np.testing.assert_allclose(o, outs[0], rtol=1e-12, atol=1e-15)
+
+
+def test_autograd_function_matches_finite_differences(cf, ctx):
+    """Central differences (h=1e-6, FP64 oracle, K fixed, matching frozen) on
+    sampled edges of workload-3-shaped pairs."""
+    w = config_graphs(3, scale=4 / 1024)
+    graphs, pa, pb = w["graphs"], w["pair_a"], w["pair_b"]
+    gs = cf.pack(ctx, graphs)
+    wt = gs.w.clone().requires_grad_(True)
+    scores = cf.CfsimScore.apply(wt, ctx, gs, pa, pb, "f32", 200, 1e-12, 8)
+    coef = torch.linspace(1.0, 2.0, len(pa), dtype=torch.float64, device="cuda")
+    (scores * coef).sum().backward()
+    g = _to_input_order(cf, gs, wt.grad.detach().cpu().numpy(), graphs)
+    # forward facts the FD holds fixed
+    b = cf.Batch(ctx, gs, pa, pb, dtype="f32", want_match=True)
+    b.run()
+    torch.cuda.synchronize()
+    res, matches = b.results(), b.matches()
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    from paper_1707_02423_amd.cfsim import concat_coo
+    _, edge_off, _, _, _ = concat_coo(graphs)
+    worst = 0.0
+    for p in range(len(pa)):
+        K, m = int(res["iters"][p]), matches[p]
+        ga, gb = graphs[pa[p]], graphs[pb[p]]
+        A = oracle.transition_matrix(ga.n, ga.src, ga.dst, ga.count)
+        B = oracle.transition_matrix(gb.n, gb.src, gb.dst, gb.count)
+        for which, G, X in (("A", ga, A), ("B", gb, B)):
+            for e in rng.choice(G.nnz, size=min(6, G.nnz), replace=False):
+                u, v = int(G.src[e]), int(G.dst[e])
+                f = []
+                for sgn in (1, -1):
+                    Xh = X.copy()
+                    Xh[u, v] += sgn * h
+                    S = oracle.coupled_iteration(Xh, B, K, -1.0)[0] if which == "A" else \
+                        oracle.coupled_iteration(A, Xh, K, -1.0)[0]
+                    f.append(sum(S[i, j] for i, j in enumerate(m) if j >= 0))
+                fd = float(coef[p]) * (f[0] - f[1]) / (2 * h)
+                off = edge_off[pa[p] if which == "A" else pb[p]]
+                worst = max(worst, abs(g[off + e] - fd) / max(1.0, abs(fd)))
+    assert worst < 5e-4, worst
