@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device copy of this size first (profiler byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); pairs would shard across GPUs "
@@ -87,6 +89,13 @@ def main():
     import paper_1707_02423_amd as cf
     from paper_1707_02423_amd import cfsim as cfm
     from cfgsynth import config_graphs
+
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * (1 << 18), dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = config_graphs(1)
     graphs, pa, pb = w["graphs"], w["pair_a"], w["pair_b"]

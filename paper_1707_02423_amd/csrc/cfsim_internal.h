@@ -185,7 +185,6 @@ struct PairJob {
     void* S_out;
     const int64_t* S_off;
     int variant;
-    int lds_bytes;
     // Workspace of gridDim.x slots of slot_elems elements each: S_{k-2} (LDS
     // kernel), or S_cur, S_next, S_{k-2} at 3 * slot_elems (global kernel).
     void* gws;

@@ -35,11 +35,12 @@ namespace {
 
 using namespace dev;
 
-// Steps a4-a6 with S in LDS (NCH = exact chunk count); S_{k-2} lives in the
+// Steps a4-a6 with S in LDS (NCH = exact chunk count); S_{k-2} lives in a
+// third LDS buffer Sp_lds when the variant's budget holds it, else in the
 // workgroup's global slot Sp.  Returns the buffer holding the final S.
 template <typename T, int NT, int NCH>
 __device__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
-                               const Lists<T>& G, bool degenerate, T* Sp, double* red) {
+                               const Lists<T>& G, bool degenerate, T* Sp, T* Sp_lds, double* red) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
     const int nR = sh.nR, nC = sh.nC;
@@ -102,21 +103,27 @@ __device__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const Pair
             continue;
         }
         // even k: normalise in place and take the step against S_{k-2}
+        // (every entry is final after the barrier above: flat, unrolled loops)
         double d2 = 0.0;
-        unsigned char* Sw = const_cast<unsigned char*>(Sb);
-        for (int i = wave; i < nR; i += NW) {
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                if (cv[ch]) {
-                    T* q = reinterpret_cast<T*>(Sw + i * rowb + col[ch] * esz);
-                    T* pq = Sp + i * nC + col[ch];
-                    const T sv = *q * inv;
-                    const T old = *pq;
-                    *q = sv;
-                    *pq = sv;
-                    const double d = (double)sv - (double)old;
-                    d2 += d * d;
-                }
+        T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
+        const int total = nR * nC;
+        if (Sp_lds) {
+#pragma unroll 4
+            for (int t = threadIdx.x; t < total; t += NT) {
+                const T sv = Sw[t] * inv;
+                const double d = (double)sv - (double)Sp_lds[t];
+                Sw[t] = sv;
+                Sp_lds[t] = sv;
+                d2 += d * d;
+            }
+        } else {
+#pragma unroll 4
+            for (int t = threadIdx.x; t < total; t += NT) {
+                const T sv = Sw[t] * inv;
+                const double d = (double)sv - (double)Sp[t];
+                Sw[t] = sv;
+                Sp[t] = sv;
+                d2 += d * d;
             }
         }
         sigma = T(1);
@@ -238,48 +245,62 @@ __device__ void match_and_write(const PairJob& J, int p, const GraphRef& A, cons
     int* rbest = G.rbest;
     int* cstate = G.cstate;
     int* cbest = G.cbest;
-    for (int r = tid; r < nR; r += NT) rstate[r] = -1;
-    for (int c = tid; c < nC; c += NT) cstate[c] = -1;
+    // Incremental rounds: a free row's best free column (and a free column's
+    // best free row) only changes when that partner gets matched, so each round
+    // recomputes just the rows/columns marked stale (best = -2); mutual bests
+    // are matched.  All state lives in LDS; three barriers per round.
+    for (int r = tid; r < nR; r += NT) {
+        rstate[r] = -1;
+        rbest[r] = -2;
+    }
+    for (int c = tid; c < nC; c += NT) {
+        cstate[c] = -1;
+        cbest[c] = -2;
+    }
     if (tid == 0) *s_count = 0;
     __syncthreads();
     const int need = min(nR, nC);
     const bool swp = sh.swap != 0;
     int done = 0;
     while (done < need) {
-        for (int r = wave; r < nR; r += NW) {
-            if (uni(rstate[r]) != -1) continue;
-            T bv = T(-1);
-            int bk = INT_MAX, bc = -1;
-            for (int c = lane; c < nC; c += kWave) {
-                if (cstate[c] == -1) {
-                    const T v = S[(long long)r * nC + c];
-                    const int key = swp ? c * nR + r : r * nC + c;
-                    if (better(v, key, bv, bk)) {
-                        bv = v;
-                        bk = key;
-                        bc = c;
+        for (int it = wave; it < nR + nC; it += NW) {
+            if (it < nR) {
+                const int r = it;
+                if (uni(rstate[r]) != -1 || uni(rbest[r]) != -2) continue;
+                T bv = T(-1);
+                int bk = INT_MAX, bc = -1;
+                for (int c = lane; c < nC; c += kWave) {
+                    if (cstate[c] == -1) {
+                        const T v = S[(long long)r * nC + c];
+                        const int key = swp ? c * nR + r : r * nC + c;
+                        if (better(v, key, bv, bk)) {
+                            bv = v;
+                            bk = key;
+                            bc = c;
+                        }
                     }
                 }
-            }
-            wave_argmax(bv, bk, bc);
-            if (lane == 0) rbest[r] = bc;
-        }
-        for (int c = tid; c < nC; c += NT) {
-            if (cstate[c] != -1) continue;
-            T bv = T(-1);
-            int bk = INT_MAX, br = -1;
-            for (int r = 0; r < nR; ++r) {
-                if (rstate[r] == -1) {
-                    const T v = S[(long long)r * nC + c];
-                    const int key = swp ? c * nR + r : r * nC + c;
-                    if (better(v, key, bv, bk)) {
-                        bv = v;
-                        bk = key;
-                        br = r;
+                wave_argmax(bv, bk, bc);
+                if (lane == 0) rbest[r] = bc;
+            } else {
+                const int c = it - nR;
+                if (uni(cstate[c]) != -1 || uni(cbest[c]) != -2) continue;
+                T bv = T(-1);
+                int bk = INT_MAX, br = -1;
+                for (int r = lane; r < nR; r += kWave) {
+                    if (rstate[r] == -1) {
+                        const T v = S[(long long)r * nC + c];
+                        const int key = swp ? c * nR + r : r * nC + c;
+                        if (better(v, key, bv, bk)) {
+                            bv = v;
+                            bk = key;
+                            br = r;
+                        }
                     }
                 }
+                wave_argmax(bv, bk, br);
+                if (lane == 0) cbest[c] = br;
             }
-            cbest[c] = br;
         }
         __syncthreads();
         for (int r = tid; r < nR; r += NT) {
@@ -293,6 +314,11 @@ __device__ void match_and_write(const PairJob& J, int p, const GraphRef& A, cons
             }
         }
         __syncthreads();
+        // stale marks: bests that were just taken by someone else
+        for (int r = tid; r < nR; r += NT)
+            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) rbest[r] = -2;
+        for (int c = tid; c < nC; c += NT)
+            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) cbest[c] = -2;
         const int now = *s_count;
         __syncthreads();
         if (now == done) break;  // no progress: only possible with non-finite S
@@ -355,18 +381,24 @@ __device__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* r
     const GraphRef C = sh.swap ? B : A;
     const int nR = sh.nR, nC = sh.nC;
     const size_t sbytes = align16((size_t)nR * nC * sizeof(T));
+    const size_t lbytes = lds_lists_bytes(nR, nC, R.nnz, C.nnz, (int)sizeof(T));
     const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
     const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
+    // S_{k-2}: third LDS buffer if it fits the variant's budget, else the global slot
+    T* Sp_lds = (3 * sbytes + lbytes <= (size_t)variant_info(J.variant, (int)sizeof(T)).lds_bytes)
+                    ? reinterpret_cast<T*>(smem + 2 * sbytes + align16(lbytes))
+                    : nullptr;
     T* Sp = reinterpret_cast<T*>(J.gws) + (size_t)blockIdx.x * (size_t)J.slot_elems;
-    for (int t = threadIdx.x; t < nR * nC; t += NT) Sp[t] = s0;
+    T* Spi = Sp_lds ? Sp_lds : Sp;
+    for (int t = threadIdx.x; t < nR * nC; t += NT) Spi[t] = s0;
     const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
     IterOut it;
     if (sh.nchunk == 1)
-        it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, Sp, red);
+        it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
     else if (NCHMAX >= 2 && sh.nchunk == 2)
-        it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, Sp, red);
+        it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
     else
-        it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, Sp, red);
+        it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
     const T* S = reinterpret_cast<const T*>(smem + (it.final_buf ? sbytes : 0));
     match_and_write<T, NT>(J, p, A, B, sh, S, G, it, res, red, s_count);
 }
