@@ -68,6 +68,73 @@ def cpu_baseline(n_pairs_total: int, sample: int, seed: int = 7):
                        f"{cores} processes, {sum(busy):.1f} s of CPU work, {wall:.1f} s wall")
 
 
+def kernel_sources_digest() -> str:
+    """SHA-256 over the HIP sources of the library (detects kernels changed since profiling)."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_1707_02423_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def traffic_of(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is none or
+    the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_workload1.txt")
+    if not os.path.exists(path):
+        return None
+    digest, found = None, None
+    with open(path) as f:
+        for ln in f:
+            parts = ln.split()
+            if len(parts) == 2 and parts[0] == "source_sha256":
+                digest = parts[1]
+            elif len(parts) >= 3 and parts[0] == "traffic_bytes_per_launch" and " ".join(parts[2:]) == kernel:
+                found = float(parts[1])
+    return found if digest == kernel_sources_digest() else None
+
+
+def plain_leg(ctx, gs, pa, pb, res, n_sub, stream):
+    """One cfsim_score launch per pair on a seeded sample, same dtype."""
+    import torch
+    from paper_1707_02423_amd import cfsim as cfm
+    rng = np.random.default_rng(11)
+    sub = rng.choice(len(pa), size=min(n_sub, len(pa)), replace=False)
+    L = cfm.lib()
+    opt = cfm.options("f32")
+    dev = gs.w.device
+    maxn = int(gs.sizes().max())
+    m_buf = torch.empty(maxn, dtype=torch.int32, device=dev)
+    r_buf = torch.empty(len(sub) * 32, dtype=torch.uint8, device=dev)
+    ws_bytes = L.cfsim_score_workspace_size(ctx.handle, maxn, maxn, ctypes.byref(opt))
+    ws_buf = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    gA = [gs.graph(int(pa[p])) for p in sub]
+    gB = [gs.graph(int(pb[p])) for p in sub]
+    sh = stream.cuda_stream
+
+    def plain_pass():
+        for k in range(len(sub)):
+            rc = L.cfsim_score(ctx.handle, ctypes.byref(gA[k]), ctypes.byref(gB[k]), ctypes.byref(opt), None,
+                               m_buf.data_ptr(), r_buf.data_ptr() + 32 * k, ws_buf.data_ptr(), ws_bytes, sh)
+            if rc != 0:
+                raise RuntimeError(L.cfsim_last_error().decode())
+    plain_pass()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    plain_pass()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = ev0.elapsed_time(ev1)
+    plain_res = r_buf.cpu().numpy().view(cfm.RESULT_DTYPE)
+    return dict(plain_value=len(sub) / (plain_ms * 1e-3), plain_pairs_timed=int(len(sub)),
+                plain_vs_batched_max_score_diff=float(np.max(np.abs(plain_res["score"] - res["score"][sub]))))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +144,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=3, help="timed eager passes for per-kernel durations")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -127,42 +195,35 @@ def main():
     nnz = np.diff(gs.edge_off)
     nA, nB = sizes[pa].astype(np.float64), sizes[pb].astype(np.float64)
     mA, mB = nnz[pa].astype(np.float64), nnz[pb].astype(np.float64)
-    flops = float(np.sum(iters * (4.0 * mA * mB + 3.0 * nA * nB)))
+    pair_flops = iters * (4.0 * mA * mB + 3.0 * nA * nB)
+    flops = float(np.sum(pair_flops))
     lds_bytes = float(np.sum(iters * (2.0 * mA * mB + nA * nB) * 4.0))
     achieved = flops / (ms * 1e-3)
 
-    # ---------------------------------------------------------------- plain
-    rng = np.random.default_rng(11)
-    sub = rng.choice(n_pairs, size=min(args.plain_pairs, n_pairs), replace=False)
-    L = cfm.lib()
-    opt = cfm.options("f32")
-    dev = gs.w.device
-    maxn = int(sizes.max())
-    S_buf = torch.empty(maxn * maxn, dtype=torch.float32, device=dev)
-    m_buf = torch.empty(maxn, dtype=torch.int32, device=dev)
-    r_buf = torch.empty(len(sub) * 32, dtype=torch.uint8, device=dev)
-    ws_bytes = L.cfsim_score_workspace_size(ctx.handle, maxn, maxn, ctypes.byref(opt))
-    ws_buf = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    gA = [gs.graph(int(pa[p])) for p in sub]
-    gB = [gs.graph(int(pb[p])) for p in sub]
-    sh = stream.cuda_stream
+    # ---------------------------------------------------------------- dominant kernel
+    # Same launches without the graph, with an event pair on each bucket's
+    # stream around its kernel; the dominant kernel is the longest bucket.
+    bucket = batch.buckets()
+    ctx.set_timing(True)
+    kms = np.zeros(cf.NUM_BUCKETS)
+    for _ in range(args.kernel_reps):
+        batch.run()
+        kms += ctx.batch_timings()
+    ctx.set_timing(False)
+    kms /= args.kernel_reps
+    dom = int(np.argmax(kms[:cf.NUM_BUCKETS - 1]))
+    dom_flops = float(np.sum(pair_flops[bucket == dom]))
+    dom_achieved = dom_flops / (kms[dom] * 1e-3)
+    kernels = {cf.bucket_kernel(v, "f32"): dict(avg_ms=float(kms[v]), pairs=int(np.sum(bucket == v)),
+                                                flops=float(np.sum(pair_flops[bucket == v])))
+               for v in range(cf.NUM_BUCKETS - 1) if np.any(bucket == v)}
 
-    def plain_pass():
-        for k in range(len(sub)):
-            rc = L.cfsim_score(ctx.handle, ctypes.byref(gA[k]), ctypes.byref(gB[k]), ctypes.byref(opt), None,
-                               m_buf.data_ptr(), r_buf.data_ptr() + 32 * k, ws_buf.data_ptr(), ws_bytes, sh)
-            if rc != 0:
-                raise RuntimeError(L.cfsim_last_error().decode())
-    plain_pass()
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    plain_pass()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    plain_ms = ev0.elapsed_time(ev1)
-    plain_value = len(sub) / (plain_ms * 1e-3)
-    plain_res = r_buf.cpu().numpy().view(cfm.RESULT_DTYPE)
-    plain_agree = float(np.max(np.abs(plain_res["score"] - res["score"][sub])))
+    # ---------------------------------------------------------------- plain
+    plain = {}
+    if args.plain_pairs > 0:
+        plain = plain_leg(ctx, gs, pa, pb, res, args.plain_pairs, stream)
+        plain["batched_over_plain"] = value / plain["plain_value"]
+    dev = gs.w.device
 
     # ---------------------------------------------------------------- verification
     ver = {}
@@ -222,16 +283,18 @@ def main():
                                "[1,1e4], 32,640 pairs, FP32 with FP64 reductions, tol 1e-12, max 200 iterations, "
                                "one HIP-graph replay of the persistent bucketed launch",
                    "pairs": n_pairs, "graphs": len(graphs), "seed": int(w["seed"])},
-        "plain_value": plain_value,
-        "plain_pairs_timed": int(len(sub)),
-        "batched_over_plain": value / plain_value,
-        "plain_vs_batched_max_score_diff": plain_agree,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": None},
+        "roofline": {"bound": "alu", "achieved": dom_achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                     "unit": "TFLOP/s", "frac": dom_achieved / FP32_VECTOR_PEAK,
+                     "traffic": traffic_of(cf.bucket_kernel(dom, "f32")),
+                     "kernel": cf.bucket_kernel(dom, "f32"), "avg_launch_ms": float(kms[dom]),
+                     "flops_per_launch": dom_flops},
+        "step_roofline": {"achieved": achieved / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK},
+        "kernels": kernels,
         "lds_roofline": {"achieved": lds_bytes / (ms * 1e-3) / 1e12, "peak": LDS_PEAK / 1e12, "unit": "TB/s",
                          "frac": lds_bytes / (ms * 1e-3) / LDS_PEAK},
         "algorithmic_flops_per_step": flops,
     }
+    line.update(plain)
     line.update(ver)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n_pairs, args.cpu_sample)

@@ -183,6 +183,56 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
                                void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Step a9 - large pairs (Section 3.2 operator at hundreds to thousands of
+ * nodes): same arguments, outputs and per-pair semantics as
+ * cfsim_score_batch, for pairs whose lists do not fit the batched kernels
+ * (those report CFSIM_INVALID_INPUT there).  S lives in the workspace (four
+ * iterates per pair, HBM); every update is one launch over the tiles of all
+ * pairs of the call, and the whole sequence (max_iter + 4 launches) is
+ * captured once into a HIP graph cached in the context.  Limits: graphs of at
+ * most 8192 nodes (set->max_nodes), at most 65535 pairs per call, max_iter at
+ * most 4096; otherwise CFSIM_E_UNSUPPORTED.  ws is a device workspace of
+ * cfsim_large_workspace_size() bytes, about 4 * n_pairs * max_nodes^2
+ * elements of opt->dtype.
+ */
+size_t cfsim_large_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set,
+                                  int64_t n_pairs, const cfsim_options* opt);
+cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set,
+                               const int32_t* pair_a, const int32_t* pair_b, int64_t n_pairs,
+                               const cfsim_options* opt, cfsim_pair_result* res,
+                               int32_t* match, const int64_t* match_off,
+                               void* S_out, const int64_t* S_off,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batch schedule and kernel timing (observability of the batched path).
+ * Every pair of a batch runs in one of CFSIM_NUM_BUCKETS buckets: 0..4 are
+ * the LDS-resident pair kernels in increasing size, 5 the global-memory pair
+ * kernel, 6 the pairs no kernel takes (they get CFSIM_INVALID_INPUT).
+ *   cfsim_batch_buckets: writes the bucket cfsim_score_batch would give each
+ *     pair to bucket[n_pairs] (device int32), on `stream`.  Same argument
+ *     rules as cfsim_score_batch; no workspace.
+ *   cfsim_bucket_kernel: the name of the kernel serving `bucket` for `dtype`
+ *     (static string, as profilers print it without namespace and argument
+ *     list); "" for bucket 6 or an out-of-range argument.
+ *   cfsim_context_set_timing: with on != 0, later cfsim_score_batch calls
+ *     launch without the cached graph and record a HIP event pair on the
+ *     caller's stream around each bucket's kernel (the bucket kernels run one
+ *     after another on that stream, as in the graph).  on = 0 returns to
+ *     graph replays.
+ *   cfsim_batch_timings: waits for the last timed call and writes each
+ *     bucket kernel's duration in milliseconds to ms[CFSIM_NUM_BUCKETS]
+ *     (host).  CFSIM_E_INVALID_ARG if no timed call was made.
+ */
+#define CFSIM_NUM_BUCKETS 7
+cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                 const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                                 int32_t* bucket, void* stream);
+const char* cfsim_bucket_kernel(int32_t bucket, int32_t dtype);
+cfsim_status cfsim_context_set_timing(cfsim_context* ctx, int32_t on);
+cfsim_status cfsim_batch_timings(cfsim_context* ctx, float* ms);
+
+/*
  * Step a10 - reverse mode: d(sum_p grad_score[p] * score_p) / d(w), added to
  * grad_w[total_edges] (device, FP64, CSR order of `set`; not cleared).  The
  * matching and the update count of each pair are held fixed (the

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libcfsim.so")
 F64, F32 = 0, 1
 RESIZE_NONE, RESIZE_BILINEAR = 0, 1
 CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT = 1, 2, 4, 8
+NUM_BUCKETS = 7  # batch buckets: 0-4 LDS kernels, 5 global-memory kernel, 6 invalid pairs
 PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
 
 STATUS_NAMES = {0: "CFSIM_OK", -1: "CFSIM_E_INVALID_ARG", -2: "CFSIM_E_BAD_GRAPH", -3: "CFSIM_E_NONFINITE",
@@ -76,6 +77,14 @@ SIGNATURES = {
     "cfsim_backward_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options), _I32]),
     "cfsim_score_backward": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
                                             _P, _P, _P, _P, _P, _P, _I32, _P, _SZ, _P]),
+    "cfsim_large_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options)]),
+    "cfsim_score_large": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
+                                         _P, _P, _P, _P, _P, _SZ, _P]),
+    "cfsim_batch_buckets": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
+                                           _P, _P]),
+    "cfsim_bucket_kernel": (ctypes.c_char_p, [_I32, _I32]),
+    "cfsim_context_set_timing": (ctypes.c_int, [_P, _I32]),
+    "cfsim_batch_timings": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
     "cfsim_topk_workspace_size": (_SZ, [_I64, _I32]),
     "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
 }
@@ -126,6 +135,16 @@ class Context:
         _check(lib().cfsim_context_create(ctypes.byref(h), int(device)))
         self.handle = h
         self.device = int(device)
+
+    def set_timing(self, on: bool):
+        """Eager batched launches with an event pair around each bucket kernel."""
+        _check(lib().cfsim_context_set_timing(self.handle, 1 if on else 0))
+
+    def batch_timings(self) -> np.ndarray:
+        """Milliseconds of each bucket kernel of the last timed batch call (waits for it)."""
+        ms = (ctypes.c_float * NUM_BUCKETS)()
+        _check(lib().cfsim_batch_timings(self.handle, ms))
+        return np.array(ms[:], dtype=np.float64)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -272,7 +291,10 @@ class Batch:
     """
 
     def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
-                 resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None):
+                 resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch"):
+        if path not in ("batch", "large"):
+            raise ValueError("path must be 'batch' (cfsim_score_batch) or 'large' (cfsim_score_large)")
+        self.path = path
         self.ctx, self.gs = ctx, gs
         self.opt = options(dtype, max_iter, tol, resize)
         dev = gs.w.device
@@ -302,15 +324,24 @@ class Batch:
             self.S = torch.empty(max(int(off[-1]), 1), dtype=_torch_dtype(self.opt), device=dev)
         self.w = w
         self.set_c = gs.c_struct(w)
-        self.ws_bytes = lib().cfsim_batch_workspace_size(ctx.handle, ctypes.byref(self.set_c), self.n_pairs,
-                                                         ctypes.byref(self.opt))
+        size_fn = lib().cfsim_batch_workspace_size if path == "batch" else lib().cfsim_large_workspace_size
+        self.ws_bytes = size_fn(ctx.handle, ctypes.byref(self.set_c), self.n_pairs, ctypes.byref(self.opt))
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
 
     def run(self, stream=None):
-        _check(lib().cfsim_score_batch(self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a),
-                                       _ptr(self.pair_b), self.n_pairs, ctypes.byref(self.opt), _ptr(self.res),
-                                       _ptr(self.match), _ptr(self.match_off), _ptr(self.S), _ptr(self.S_off),
-                                       _ptr(self.ws), self.ws_bytes, _stream(stream)))
+        fn = lib().cfsim_score_batch if self.path == "batch" else lib().cfsim_score_large
+        _check(fn(self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a),
+                  _ptr(self.pair_b), self.n_pairs, ctypes.byref(self.opt), _ptr(self.res),
+                  _ptr(self.match), _ptr(self.match_off), _ptr(self.S), _ptr(self.S_off),
+                  _ptr(self.ws), self.ws_bytes, _stream(stream)))
+
+    def buckets(self, stream=None) -> np.ndarray:
+        """The bucket (kernel) the plan gives each pair (see bucket_kernel)."""
+        out = torch.empty(max(self.n_pairs, 1), dtype=torch.int32, device=self.pair_a.device)
+        _check(lib().cfsim_batch_buckets(self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a),
+                                         _ptr(self.pair_b), self.n_pairs, ctypes.byref(self.opt), _ptr(out),
+                                         _stream(stream)))
+        return out[: self.n_pairs].cpu().numpy()
 
     def topk(self, k: int, stream=None):
         """Top-k of this batch's scores, on the device (call after run())."""
@@ -327,6 +358,12 @@ class Batch:
     def S_list(self):
         S = self.S.cpu().numpy()
         return [S[o:o + a * b].reshape(b, a) for o, a, b in zip(self.S_off_h, self.nA, self.nB)]
+
+
+def bucket_kernel(bucket: int, dtype="f32") -> str:
+    """Name of the kernel that serves a batch bucket ("" for the invalid bucket)."""
+    d = {"f64": F64, "f32": F32}[dtype] if isinstance(dtype, str) else int(dtype)
+    return lib().cfsim_bucket_kernel(int(bucket), d).decode()
 
 
 def topk(ctx: Context, scores: torch.Tensor, k: int, stride: int = 1, n: int | None = None, stream=None):
@@ -391,9 +428,9 @@ class CfsimScore(torch.autograd.Function):
 
 
 def score_batch(ctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, resize="none", want_match=True,
-                want_S=False):
-    """Batched path: run once, synchronise, return (results, matches, S list)."""
-    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S)
+                want_S=False, path="batch"):
+    """Batched (or large-pair) path: run once, synchronise, return (results, matches, S list)."""
+    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S, path=path)
     b.run()
     torch.cuda.synchronize()
     return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)

@@ -15,13 +15,17 @@ struct cfsim_context {
     int device = 0;
     int num_cus = 0;
     int grid[2][cfsim::kBucketGlobal + 1] = {};  // persistent grid per [dtype][LDS variant | global]
-    hipStream_t cap = nullptr;              // capture stream of the batch graph
-    hipStream_t side[cfsim::kBuckets] = {};  // one stream per bucket (fork/join)
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[cfsim::kBuckets] = {};
+    hipStream_t cap = nullptr;              // capture stream of the cached graphs
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<unsigned char> key;         // arguments the cached graph was built for
+    hipGraph_t large_graph = nullptr;       // cached graph of the large-pair sequence
+    hipGraphExec_t large_exec = nullptr;
+    std::vector<unsigned char> large_key;
+    int timing = 0;                         // eager launches with per-bucket event pairs
+    int timed = 0;                          // a timed call has been enqueued
+    hipEvent_t t0[cfsim::kBuckets] = {};
+    hipEvent_t t1[cfsim::kBuckets] = {};
 };
 
 namespace {
@@ -196,7 +200,7 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device) {
         delete ctx;
         return hip_fail(e, "hipDeviceGetAttribute");
     }
-    if ((e = cfsim::set_kernel_attributes()) != 0) {
+    if ((e = cfsim::set_kernel_attributes()) != 0 || (e = cfsim::set_large_attributes()) != 0) {
         delete ctx;
         return hip_fail(e, "hipFuncSetAttribute");
     }
@@ -216,15 +220,6 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device) {
         delete ctx;
         return hip_fail(e, "hipStreamCreateWithFlags");
     }
-    e = (int)hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
-    for (int v = 0; v < cfsim::kBuckets && e == 0; ++v) {
-        e = (int)hipStreamCreateWithFlags(&ctx->side[v], hipStreamNonBlocking);
-        if (e == 0) e = (int)hipEventCreateWithFlags(&ctx->join[v], hipEventDisableTiming);
-    }
-    if (e != 0) {
-        cfsim_context_destroy(ctx);
-        return hip_fail(e, "stream/event creation");
-    }
     *out = ctx;
     return ok();
 }
@@ -233,12 +228,13 @@ void cfsim_context_destroy(cfsim_context* ctx) {
     if (!ctx) return;
     if (ctx->exec) (void)hipGraphExecDestroy(ctx->exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->large_exec) (void)hipGraphExecDestroy(ctx->large_exec);
+    if (ctx->large_graph) (void)hipGraphDestroy(ctx->large_graph);
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (int v = 0; v < cfsim::kBuckets; ++v) {
-        if (ctx->side[v]) (void)hipStreamDestroy(ctx->side[v]);
-        if (ctx->join[v]) (void)hipEventDestroy(ctx->join[v]);
+        if (ctx->t0[v]) (void)hipEventDestroy(ctx->t0[v]);
+        if (ctx->t1[v]) (void)hipEventDestroy(ctx->t1[v]);
     }
-    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     delete ctx;
 }
 
@@ -358,7 +354,7 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
 static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
                          int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
-                         hipStream_t st) {
+                         hipStream_t st, bool timed) {
     const int esize = esize_of(opt->dtype);
     const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
     cfsim::PlanJob plan;
@@ -387,12 +383,10 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
     job.S_out = S_out;
     job.S_off = S_off;
     const int d = dtype_index(opt->dtype);
-    // Fork: every bucket kernel runs on its own stream after the plan, so the
-    // tail of one bucket overlaps the next; the caller's stream joins them all.
-    if ((e = (int)hipEventRecord(ctx->fork, st)) != 0) return e;
-    for (int v = cfsim::kBucketInvalid; v >= 0; --v) {
-        hipStream_t sv = ctx->side[v];
-        if ((e = (int)hipStreamWaitEvent(sv, ctx->fork, 0)) != 0) return e;
+    // The bucket kernels run one after another on the caller's stream, each
+    // with the whole device: a bucket's persistent grid drains its queue
+    // longest pair first, so its tail is about one pair long.
+    for (int v = 0; v < cfsim::kBuckets; ++v) {
         job.bounds = b.bounds + 2 * v;
         job.queue = b.queues + v;
         job.variant = v;
@@ -406,9 +400,9 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
             job.slot_elems = global_slot_elems(set->max_nodes);
             grid = ctx->grid[d][v];
         }
-        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, grid, sv)) != 0) return e;
-        if ((e = (int)hipEventRecord(ctx->join[v], sv)) != 0) return e;
-        if ((e = (int)hipStreamWaitEvent(st, ctx->join[v], 0)) != 0) return e;
+        if (timed && (e = (int)hipEventRecord(ctx->t0[v], st)) != 0) return e;
+        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, grid, st)) != 0) return e;
+        if (timed && (e = (int)hipEventRecord(ctx->t1[v], st)) != 0) return e;
     }
     return 0;
 }
@@ -438,9 +432,11 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     const char* nog = getenv("CFSIM_NO_GRAPH");
-    if (nog && nog[0] == '1') {
-        e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+    if (ctx->timing || (nog && nog[0] == '1')) {
+        e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st,
+                          ctx->timing != 0);
         if (e != 0) return hip_fail(e, "batch launch");
+        if (ctx->timing) ctx->timed = 1;
         return ok();
     }
 
@@ -469,7 +465,7 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
         if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
             return hip_fail(e, "hipStreamBeginCapture");
         const int le = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
-                                     ws, ctx->cap);
+                                     ws, ctx->cap, false);
         hipGraph_t g = nullptr;
         e = (int)hipStreamEndCapture(ctx->cap, &g);
         if (le != 0) {
@@ -487,6 +483,194 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
         ctx->key = key;
     }
     if ((e = (int)hipGraphLaunch(ctx->exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
+    return ok();
+}
+
+cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                 const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, int32_t* bucket,
+                                 void* stream) {
+    cfsim_status s;
+    if ((s = check_set(set)) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
+    if (n_pairs > 0 && (!pair_a || !pair_b || !bucket))
+        return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or bucket is NULL");
+    if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_pairs == 0) return ok();
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    cfsim::PlanJob plan{};
+    plan.set = ref_of(set);
+    plan.pair_a = pair_a;
+    plan.pair_b = pair_b;
+    plan.n_pairs = n_pairs;
+    plan.esize = esize_of(opt->dtype);
+    plan.slot_elems = global_slot_elems(set->max_nodes);
+    e = cfsim::launch_buckets(plan, bucket, static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "bucket launch");
+    return ok();
+}
+
+const char* cfsim_bucket_kernel(int32_t bucket, int32_t dtype) { return cfsim::bucket_kernel_name(bucket, dtype); }
+
+cfsim_status cfsim_context_set_timing(cfsim_context* ctx, int32_t on) {
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (on && !ctx->t0[0]) {
+        int e = (int)hipSetDevice(ctx->device);
+        for (int v = 0; v < cfsim::kBuckets && e == 0; ++v) {
+            e = (int)hipEventCreate(&ctx->t0[v]);
+            if (e == 0) e = (int)hipEventCreate(&ctx->t1[v]);
+        }
+        if (e != 0) return hip_fail(e, "hipEventCreate");
+    }
+    ctx->timing = on != 0;
+    return ok();
+}
+
+cfsim_status cfsim_batch_timings(cfsim_context* ctx, float* ms) {
+    if (!ctx || !ms) return fail(CFSIM_E_INVALID_ARG, "context or ms is NULL");
+    if (!ctx->timed) return fail(CFSIM_E_INVALID_ARG, "no timed cfsim_score_batch call was made");
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    for (int v = 0; v < cfsim::kBuckets; ++v) {
+        if ((e = (int)hipEventSynchronize(ctx->t1[v])) != 0) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.0f;
+        if ((e = (int)hipEventElapsedTime(&t, ctx->t0[v], ctx->t1[v])) != 0) return hip_fail(e, "hipEventElapsedTime");
+        ms[v] = t;
+    }
+    return ok();
+}
+
+// ------------------------------------------------------------------ large pairs (a9)
+// Workspace: state[n_pairs] | tile_off[n_pairs + 1] | done[n_pairs]
+//   | part_nu, part_delta [n_pairs * large_tiles(max_nodes)] | 4 iterates per pair
+static size_t large_ws_bytes(int64_t n_pairs, int max_nodes, int esize) {
+    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(max_nodes);
+    return align256((size_t)n_pairs * sizeof(cfsim::LargeState)) + align256((size_t)(n_pairs + 1) * 8) +
+           align256((size_t)n_pairs * 4) + 2 * align256(tiles * 8) +
+           (size_t)n_pairs * 4 * (size_t)global_slot_elems(max_nodes) * (size_t)esize;
+}
+
+size_t cfsim_large_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
+                                  const cfsim_options* opt) {
+    (void)ctx;
+    if (n_pairs < 1 || !set || !opt || set->max_nodes < 1 || set->max_nodes > cfsim::kLargeMaxNodes) return 0;
+    return large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype));
+}
+
+static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                         hipStream_t st) {
+    cfsim::LargeJob J{};
+    J.set = ref_of(set);
+    J.pair_a = pair_a;
+    J.pair_b = pair_b;
+    J.n_pairs = (int)n_pairs;
+    J.max_nodes = set->max_nodes;
+    J.max_iter = opt->max_iter;
+    J.tol = opt->tol;
+    J.res = res;
+    J.match = match;
+    J.match_off = match_off;
+    J.S_out = S_out;
+    J.S_off = S_off;
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(set->max_nodes);
+    J.st = reinterpret_cast<cfsim::LargeState*>(p);
+    p += align256((size_t)n_pairs * sizeof(cfsim::LargeState));
+    J.tile_off = reinterpret_cast<long long*>(p);
+    p += align256((size_t)(n_pairs + 1) * 8);
+    J.done = reinterpret_cast<int*>(p);
+    p += align256((size_t)n_pairs * 4);
+    J.part_nu = reinterpret_cast<double*>(p);
+    p += align256(tiles * 8);
+    J.part_delta = reinterpret_cast<double*>(p);
+    p += align256(tiles * 8);
+    J.bufs = p;
+    J.slot_elems = global_slot_elems(set->max_nodes);
+    return cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)), st);
+}
+
+cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                               const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                               cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                               const int64_t* S_off, void* ws, size_t ws_bytes, void* stream) {
+    cfsim_status s;
+    if ((s = check_set(set)) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > 65535) return fail(CFSIM_E_UNSUPPORTED, "more than 65535 pairs in one large-pair call");
+    if (n_pairs > 0 && (!pair_a || !pair_b || !res))
+        return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or res is NULL");
+    if ((match == nullptr) != (match_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
+    if ((S_out == nullptr) != (S_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
+    if (set->max_nodes > cfsim::kLargeMaxNodes)
+        return fail(CFSIM_E_UNSUPPORTED, "max_nodes above %d for the large-pair path", cfsim::kLargeMaxNodes);
+    if (opt->max_iter > 4096) return fail(CFSIM_E_UNSUPPORTED, "max_iter above 4096 for the large-pair path");
+    if (n_pairs == 0) {
+        if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+        return ok();
+    }
+    const size_t need = large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype));
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char* nog = getenv("CFSIM_NO_GRAPH");
+    if (nog && nog[0] == '1') {
+        e = enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+        if (e != 0) return hip_fail(e, "large-pair launch");
+        return ok();
+    }
+    std::vector<unsigned char> key;
+    append_key(key, *set);
+    append_key(key, pair_a);
+    append_key(key, pair_b);
+    append_key(key, n_pairs);
+    append_key(key, *opt);
+    append_key(key, res);
+    append_key(key, match);
+    append_key(key, match_off);
+    append_key(key, S_out);
+    append_key(key, S_off);
+    append_key(key, ws);
+    if (!ctx->large_exec || key != ctx->large_key) {
+        if (ctx->large_exec) {
+            (void)hipGraphExecDestroy(ctx->large_exec);
+            ctx->large_exec = nullptr;
+        }
+        if (ctx->large_graph) {
+            (void)hipGraphDestroy(ctx->large_graph);
+            ctx->large_graph = nullptr;
+        }
+        ctx->large_key.clear();
+        if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
+            return hip_fail(e, "hipStreamBeginCapture");
+        const int le =
+            enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, ctx->cap);
+        hipGraph_t g = nullptr;
+        e = (int)hipStreamEndCapture(ctx->cap, &g);
+        if (le != 0) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le, "large-pair launch during capture");
+        }
+        if (e != 0) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        if ((e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != 0) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        ctx->large_graph = g;
+        ctx->large_exec = x;
+        ctx->large_key = key;
+    }
+    if ((e = (int)hipGraphLaunch(ctx->large_exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
     return ok();
 }
 

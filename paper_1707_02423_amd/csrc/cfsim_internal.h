@@ -199,6 +199,7 @@ struct PairJob {
 constexpr int kBucketGlobal = kNumVariants;
 constexpr int kBucketInvalid = kNumVariants + 1;
 constexpr int kBuckets = kNumVariants + 2;
+static_assert(kBuckets == CFSIM_NUM_BUCKETS, "bucket count of the C ABI");
 struct PlanJob {
     SetRef set;
     const int32_t* pair_a;
@@ -216,6 +217,8 @@ struct PlanJob {
 // kernel; kBucketInvalid: marks the bucket's pairs invalid.
 int launch_pair_lds(int variant, int dtype, const PairJob& job, int grid, hipStream_t stream);
 int launch_plan(const PlanJob& job, hipStream_t stream);
+int launch_buckets(const PlanJob& job, int32_t* bucket, hipStream_t stream);  // bucket of every pair
+const char* bucket_kernel_name(int bucket, int dtype);
 int set_kernel_attributes();
 int occupancy_of(int variant, int dtype, int* blocks);  // variant may be kBucketGlobal
 
@@ -238,6 +241,46 @@ struct PackJob {
     int32_t* csrpos;   // [total_edges] workspace
 };
 int launch_pack(const PackJob& job, hipStream_t stream);
+
+// Large pairs (large.hip): per-pair state and the launch descriptor.
+struct LargeState {
+    int nA, nB;
+    int ntiles;          // tiles of Y (32 rows x 64 columns)
+    int active;          // still iterating
+    unsigned status;     // CFSIM_* bits once decided
+    int final_step;      // k of the returned iterate
+    double nu, delta;    // reported norm and last even-step change
+    double nu_k[4];      // nu_k of the iterate held in buffer k % 4 (1 for S_0)
+};
+
+struct LargeJob {
+    SetRef set;
+    const int32_t* pair_a;
+    const int32_t* pair_b;
+    int n_pairs;
+    int max_nodes;
+    int max_iter;
+    double tol;
+    cfsim_pair_result* res;
+    int32_t* match;
+    const int64_t* match_off;
+    void* S_out;
+    const int64_t* S_off;
+    // workspace
+    LargeState* st;      // [n_pairs]
+    long long* tile_off; // [n_pairs + 1]
+    int* done;           // [n_pairs] tiles finished in the current launch
+    double* part_nu;     // [tiles] squared-norm partials of Y
+    double* part_delta;  // [tiles] squared partials of S_{k-1} - S_{k-3}
+    void* bufs;          // [n_pairs][4][slot_elems] rotating iterates
+    long long slot_elems;
+};
+
+constexpr int kLargeMaxNodes = 8192;  // bound of the finish kernel's LDS matching state
+__host__ __device__ inline long long large_tiles(int n) { return (long long)((n + 31) / 32) * ((n + 63) / 64); }
+int large_step_grid(int num_cus);
+int set_large_attributes();
+int launch_large(int dtype, const LargeJob& job, int grid, hipStream_t stream);
 
 // Adjoint (adjoint.hip).
 long long backward_slot_bytes(int max_iter, int ckpt, long long slot_elems, int esize);

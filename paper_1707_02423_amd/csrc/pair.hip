@@ -547,6 +547,14 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(PlanJob P) {
     }
 }
 
+__global__ __launch_bounds__(256) void buckets_kernel(PlanJob P, int32_t* bucket) {
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < P.n_pairs; p += (int64_t)gridDim.x * 256) {
+        int b, c;
+        classify(P, p, &b, &c);
+        bucket[p] = b;
+    }
+}
+
 template <typename T, int NT, int NCH>
 const void* kernel_ptr() {
     return reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
@@ -594,6 +602,25 @@ int launch_pair_lds(int variant, int dtype, const PairJob& job, int grid, hipStr
 int launch_plan(const PlanJob& job, hipStream_t stream) {
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(kPlanThreads), 0, stream, job);
     return (int)hipGetLastError();
+}
+
+int launch_buckets(const PlanJob& job, int32_t* bucket, hipStream_t stream) {
+    const int64_t blocks = (job.n_pairs + 255) / 256;
+    hipLaunchKernelGGL(buckets_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(256), 0, stream, job,
+                       bucket);
+    return (int)hipGetLastError();
+}
+
+// Kernel names as profilers list them (template arguments as in variant_kernel).
+const char* bucket_kernel_name(int bucket, int dtype) {
+    static const char* const f64[kBucketGlobal + 1] = {
+        "pair_lds_kernel<double, 64, 1>", "pair_lds_kernel<double, 256, 2>", "pair_lds_kernel<double, 512, 2>",
+        "pair_lds_kernel<double, 1024, 2>", "pair_lds_kernel<double, 1024, 4>", "pair_global_kernel<double>"};
+    static const char* const f32[kBucketGlobal + 1] = {
+        "pair_lds_kernel<float, 64, 2>", "pair_lds_kernel<float, 256, 4>", "pair_lds_kernel<float, 512, 2>",
+        "pair_lds_kernel<float, 1024, 2>", "pair_lds_kernel<float, 1024, 4>", "pair_global_kernel<float>"};
+    if (bucket < 0 || bucket > kBucketGlobal || (dtype != CFSIM_F64 && dtype != CFSIM_F32)) return "";
+    return dtype == CFSIM_F64 ? f64[bucket] : f32[bucket];
 }
 
 int set_kernel_attributes() {

@@ -177,3 +177,53 @@ def test_topk_validation():
     assert L.cfsim_topk(None, P, 10, 1, 4, P, P, P, 1 << 20, None) == -1
     assert "context" in L.cfsim_last_error().decode()
     assert L.cfsim_topk_workspace_size(65536, 16) >= 16 * 16 * 16
+
+
+def test_bucket_and_timing_validation():
+    L = cf.lib()
+    s = _set()
+    opt = cf.options("f32")
+    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, -1, ctypes.byref(opt), 0x1000, None) == -1
+    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), None, None) == -1
+    assert "bucket" in L.cfsim_last_error().decode()
+    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None) == -1
+    assert "context" in L.cfsim_last_error().decode()
+    assert L.cfsim_context_set_timing(None, 1) == -1
+    assert L.cfsim_batch_timings(None, None) == -1
+
+
+def test_bucket_kernel_names():
+    assert cf.NUM_BUCKETS == 7
+    names = [cf.bucket_kernel(b, "f32") for b in range(cf.NUM_BUCKETS)]
+    assert names[0].startswith("pair_lds_kernel<float, 64,") and names[5] == "pair_global_kernel<float>"
+    assert names[6] == "" and cf.bucket_kernel(-1) == "" and cf.bucket_kernel(0, 7) == ""
+    assert all("double" in cf.bucket_kernel(b, "f64") for b in range(6))
+    assert len(set(names[:6])) == 6
+
+
+@pytest.mark.parametrize("kw,n_pairs,ws,opt_kw,code,text", [
+    ({}, -1, 1 << 40, {}, -1, "n_pairs"),
+    ({}, 70000, 1 << 40, {}, -6, "65535"),
+    (dict(max_nodes=9000), 5, 1 << 40, {}, -6, "8192"),
+    ({}, 5, 1 << 40, dict(max_iter=5000), -6, "4096"),
+    ({}, 5, 16, {}, -5, "workspace"),
+    ({}, 5, 1 << 40, {}, -1, "context"),
+])
+def test_large_validation(kw, n_pairs, ws, opt_kw, code, text):
+    L = cf.lib()
+    s = _set(**kw)
+    opt = cf.options("f32", **opt_kw)
+    got = L.cfsim_score_large(None, ctypes.byref(s), 0x1000, 0x1000, n_pairs, ctypes.byref(opt), 0x1000, None, None,
+                              None, None, 0x1000, ws, None)
+    assert got == code
+    assert text in L.cfsim_last_error().decode()
+
+
+def test_large_workspace_size():
+    L = cf.lib()
+    s = _set(max_nodes=2048)
+    opt = cf.options("f32")
+    one = L.cfsim_large_workspace_size(None, ctypes.byref(s), 1, ctypes.byref(opt))
+    assert one >= 4 * 2048 * 2048 * 4
+    assert L.cfsim_large_workspace_size(None, ctypes.byref(s), 64, ctypes.byref(opt)) >= 64 * 4 * 2048 * 2048 * 4
+    assert L.cfsim_large_workspace_size(None, ctypes.byref(_set(max_nodes=9000)), 1, ctypes.byref(opt)) == 0

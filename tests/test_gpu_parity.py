@@ -269,3 +269,35 @@ def test_workload1_full_size_sampled(cf, ctx):
         assert rel_err(S, ref.S) <= 1e-5
         m = b.match[int(b.match_off_h[p]):int(b.match_off_h[p]) + nB].cpu().numpy()
         check_matching(S, m, ref.S)
+
+
+def test_batch_buckets_and_timed_launch(cf, ctx):
+    rng = np.random.default_rng(12)
+    sizes = [4, 16, 40, 70, 100, 128, 200]
+    graphs = [make_cfg(n, Grammar(counts="trip"), rng) for n in sizes]
+    pa, pb = np.triu_indices(len(graphs), k=0)
+    pa = np.concatenate([pa, [0, 99]]).astype(np.int32)
+    pb = np.concatenate([pb, [-3, 1]]).astype(np.int32)
+    gs = cf.pack(ctx, graphs)
+    b = cf.Batch(ctx, gs, pa, pb, dtype="f32", want_S=True)
+    bk = b.buckets()
+    assert bk.shape == (len(pa),) and np.all((bk >= 0) & (bk < cf.NUM_BUCKETS))
+    assert bk[-1] == 6 and bk[-2] == 6 and np.all(bk[:-2] != 6)
+    # larger pairs never land in a smaller bucket than a smaller pair of the same shape class
+    area = np.array([sizes[a] * sizes[c] for a, c in zip(pa[:-2], pb[:-2])])
+    assert bk[:-2][np.argmax(area)] >= bk[:-2][np.argmin(area)]
+    b.run()
+    torch.cuda.synchronize()
+    r_graph, S_graph = b.results().copy(), b.S.clone()
+    ctx.set_timing(True)
+    try:
+        b.res.zero_()
+        b.run()
+        ms = ctx.batch_timings()
+    finally:
+        ctx.set_timing(False)
+    assert b.results().tobytes() == r_graph.tobytes() and torch.equal(b.S, S_graph)
+    used = np.unique(bk[bk < 6])
+    assert ms.shape == (cf.NUM_BUCKETS,) and np.all(ms >= 0)
+    assert np.all(ms[used] > 0), ms
+    assert np.all(r_graph["status"][bk == 6] == cf.INVALID_INPUT)
