@@ -69,14 +69,14 @@ def cpu_baseline(n_pairs_total: int, sample: int, seed: int = 7):
 
 
 def kernel_sources_digest() -> str:
-    """SHA-256 over the HIP sources of the library (detects kernels changed since profiling)."""
+    """SHA-256 over the sources the batched pair kernels are built from
+    (detects kernels changed since their counters were taken)."""
     import hashlib
     d = os.path.join(ROOT, "paper_1707_02423_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(d, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in ("cfsim_internal.h", "pair_device.h", "pair.hip"):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 

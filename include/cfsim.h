@@ -154,8 +154,14 @@ cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_node
 
 /*
  * Steps a2-a7 for one pair (plain path, one launch): S_out (n_B x n_A
- * row-major, opt->dtype; or n_M x n_M when resized), match_out[n_B] (or [n_M])
- * and res[1] are device memory; S_out and match_out may be NULL.
+ * row-major, opt->dtype; or n_M x n_M, n_M = max(n_A, n_B), when resized),
+ * match_out[n_B] (or [n_M]) and res[1] are device memory; S_out and
+ * match_out may be NULL.  With opt->resize = CFSIM_RESIZE_BILINEAR
+ * (Section 3, Section 3.1: the smaller transition matrix X becomes
+ * R X R^T with the order-1 interpolation R from its m nodes to n_M points
+ * at p (m - 1) / (n_M - 1)) the pair runs on the tiled path of
+ * cfsim_score_large (a short launch sequence instead of one launch) and
+ * needs n_M <= 8192 and max_iter <= 4096.
  */
 size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b,
                                   const cfsim_options* opt);
@@ -172,6 +178,9 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
  * Device buffers: pair_a/pair_b[n_pairs], res[n_pairs]; optional (NULL to
  * skip): match with match_off[n_pairs] (element offset of pair p's n_B
  * entries), S_out with S_off[n_pairs] (element offset of pair p's S).
+ * Resized calls (opt->resize = CFSIM_RESIZE_BILINEAR) run every pair on the
+ * tiled path of cfsim_score_large; S and match of pair p then have n_M x n_M
+ * and n_M entries, n_M = max(n_A, n_B).
  */
 size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set,
                                   int64_t n_pairs, const cfsim_options* opt);
@@ -186,14 +195,16 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
  * Step a9 - large pairs (Section 3.2 operator at hundreds to thousands of
  * nodes): same arguments, outputs and per-pair semantics as
  * cfsim_score_batch, for pairs whose lists do not fit the batched kernels
- * (those report CFSIM_INVALID_INPUT there).  S lives in the workspace (four
- * iterates per pair, HBM); every update is one launch over the tiles of all
- * pairs of the call, and the whole sequence (max_iter + 4 launches) is
- * captured once into a HIP graph cached in the context.  Limits: graphs of at
- * most 8192 nodes (set->max_nodes), at most 65535 pairs per call, max_iter at
- * most 4096; otherwise CFSIM_E_UNSUPPORTED.  ws is a device workspace of
- * cfsim_large_workspace_size() bytes, about 4 * n_pairs * max_nodes^2
- * elements of opt->dtype.
+ * (those report CFSIM_INVALID_INPUT there).  The iterates live in the
+ * workspace (HBM); every update is one launch over the tiles of all pairs of
+ * the call, and the whole sequence (max_iter + 4 launches, twice as many
+ * updates launches with resize) is captured once into a HIP graph cached in
+ * the context.  This tiled path also serves every resized pair (opt->resize =
+ * CFSIM_RESIZE_BILINEAR) of cfsim_score and cfsim_score_batch.  Limits:
+ * graphs of at most 8192 nodes (set->max_nodes), max_iter at most 4096;
+ * otherwise CFSIM_E_UNSUPPORTED.  ws is a device workspace of
+ * cfsim_large_workspace_size() bytes, about 4 (6 with resize) * n_pairs *
+ * max_nodes^2 elements of opt->dtype.
  */
 size_t cfsim_large_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set,
                                   int64_t n_pairs, const cfsim_options* opt);

@@ -261,8 +261,11 @@ def score(ctx: Context, gs: GraphSet, a: int, b: int, dtype="f64", max_iter=200,
     opt = options(dtype, max_iter, tol, resize)
     A, B = gs.graph(a), gs.graph(b)
     dev = gs.w.device
-    S = torch.empty(B.n * A.n, dtype=_torch_dtype(opt), device=dev) if want_S else None
-    match = torch.empty(B.n, dtype=torch.int32, device=dev)
+    nA, nB = A.n, B.n
+    if opt.resize == RESIZE_BILINEAR:  # S is n_M x n_M, n_M = max(n_A, n_B)
+        nA = nB = max(A.n, B.n)
+    S = torch.empty(nB * nA, dtype=_torch_dtype(opt), device=dev) if want_S else None
+    match = torch.empty(nB, dtype=torch.int32, device=dev)
     res = torch.empty(32, dtype=torch.uint8, device=dev)
     ws_bytes = lib().cfsim_score_workspace_size(ctx.handle, A.n, B.n, ctypes.byref(opt))
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
@@ -270,7 +273,7 @@ def score(ctx: Context, gs: GraphSet, a: int, b: int, dtype="f64", max_iter=200,
                              _ptr(res), _ptr(ws), ws_bytes, _stream(stream)))
     out = dict(S=S, match=match, res=res)
     if sync:
-        return finish_single(out, B.n, A.n)
+        return finish_single(out, nB, nA)
     return out
 
 
@@ -310,6 +313,9 @@ class Batch:
             ok = (idx >= 0) & (idx < gs.n_graphs)
             return np.where(ok, sizes[np.clip(idx, 0, gs.n_graphs - 1)], 0).astype(np.int64)
         nA, nB = size_of(self.pair_a_h), size_of(self.pair_b_h)
+        if self.opt.resize == RESIZE_BILINEAR:  # S is n_M x n_M, n_M = max(n_A, n_B)
+            nM = np.where((nA > 0) & (nB > 0), np.maximum(nA, nB), 0)
+            nA, nB = nM, nM
         self.nA, self.nB = nA, nB
         self.match = self.match_off = self.S = self.S_off = None
         if want_match:

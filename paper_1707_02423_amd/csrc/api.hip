@@ -63,8 +63,6 @@ cfsim_status check_options(const cfsim_options* o) {
     if (o->resize != CFSIM_RESIZE_NONE && o->resize != CFSIM_RESIZE_BILINEAR)
         return fail(CFSIM_E_INVALID_ARG, "resize must be CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR");
     if (o->flags != 0) return fail(CFSIM_E_INVALID_ARG, "flags must be 0");
-    if (o->resize == CFSIM_RESIZE_BILINEAR)
-        return fail(CFSIM_E_UNSUPPORTED, "bilinear resize is not available in this build");
     return CFSIM_OK;
 }
 
@@ -176,6 +174,123 @@ template <typename X>
 void append_key(std::vector<unsigned char>& k, const X& x) {
     const unsigned char* p = reinterpret_cast<const unsigned char*>(&x);
     k.insert(k.end(), p, p + sizeof(X));
+}
+
+// Large-pair (tiled) workspace: state[n_pairs] | tile_off[n_pairs + 1]
+//   | done[n_pairs] | part_nu, part_delta [n_pairs * large_tiles(max_nodes)]
+//   | nslots iterate slots of max_nodes^2 per pair (4, or 6 when resized)
+int large_nslots(const cfsim_options* o) { return o->resize == CFSIM_RESIZE_BILINEAR ? 6 : 4; }
+
+size_t large_ws_bytes(int64_t n_pairs, int max_nodes, int esize, int nslots) {
+    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(max_nodes);
+    return align256((size_t)n_pairs * sizeof(cfsim::LargeState)) + align256((size_t)(n_pairs + 1) * 8) +
+           align256((size_t)n_pairs * 4) + 2 * align256(tiles * 8) +
+           (size_t)n_pairs * nslots * (size_t)global_slot_elems(max_nodes) * (size_t)esize;
+}
+
+// Options, outputs and workspace of a tiled-path launch (pairs filled by the caller).
+cfsim::LargeJob large_job(const cfsim_options* opt, int64_t n_pairs, int max_nodes, cfsim_pair_result* res,
+                          int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws) {
+    cfsim::LargeJob J{};
+    J.n_pairs = (int)n_pairs;
+    J.max_nodes = max_nodes;
+    J.max_iter = opt->max_iter;
+    J.tol = opt->tol;
+    J.resize = opt->resize == CFSIM_RESIZE_BILINEAR;
+    J.res = res;
+    J.match = match;
+    J.match_off = match_off;
+    J.S_out = S_out;
+    J.S_off = S_off;
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(max_nodes);
+    J.st = reinterpret_cast<cfsim::LargeState*>(p);
+    p += align256((size_t)n_pairs * sizeof(cfsim::LargeState));
+    J.tile_off = reinterpret_cast<long long*>(p);
+    p += align256((size_t)(n_pairs + 1) * 8);
+    J.done = reinterpret_cast<int*>(p);
+    p += align256((size_t)n_pairs * 4);
+    J.part_nu = reinterpret_cast<double*>(p);
+    p += align256(tiles * 8);
+    J.part_delta = reinterpret_cast<double*>(p);
+    p += align256(tiles * 8);
+    J.bufs = p;
+    J.nslots = large_nslots(opt);
+    J.slot_elems = global_slot_elems(max_nodes);
+    return J;
+}
+
+// Replays the graph cached in (graph, exec, cached_key) when `key` matches,
+// else captures `enqueue` on the context's capture stream first.
+template <typename F>
+cfsim_status replay_or_capture(cfsim_context* ctx, hipGraph_t* graph, hipGraphExec_t* exec,
+                               std::vector<unsigned char>* cached_key, const std::vector<unsigned char>& key,
+                               hipStream_t st, F enqueue) {
+    int e;
+    if (!*exec || key != *cached_key) {
+        if (*exec) {
+            (void)hipGraphExecDestroy(*exec);
+            *exec = nullptr;
+        }
+        if (*graph) {
+            (void)hipGraphDestroy(*graph);
+            *graph = nullptr;
+        }
+        cached_key->clear();
+        if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
+            return hip_fail(e, "hipStreamBeginCapture");
+        const int le = enqueue(ctx->cap);
+        hipGraph_t g = nullptr;
+        e = (int)hipStreamEndCapture(ctx->cap, &g);
+        if (le != 0) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(le, "launch during capture");
+        }
+        if (e != 0) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        if ((e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != 0) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        *graph = g;
+        *exec = x;
+        *cached_key = key;
+    }
+    if ((e = (int)hipGraphLaunch(*exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
+    return ok();
+}
+
+bool graphs_disabled() {
+    const char* nog = getenv("CFSIM_NO_GRAPH");
+    return nog && nog[0] == '1';
+}
+
+std::vector<unsigned char> set_call_key(const cfsim_graph_set* set, const int32_t* pair_a, const int32_t* pair_b,
+                                        int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                                        int32_t* match, const int64_t* match_off, void* S_out,
+                                        const int64_t* S_off, void* ws) {
+    std::vector<unsigned char> key;
+    append_key(key, *set);
+    append_key(key, pair_a);
+    append_key(key, pair_b);
+    append_key(key, n_pairs);
+    append_key(key, *opt);
+    append_key(key, res);
+    append_key(key, match);
+    append_key(key, match_off);
+    append_key(key, S_out);
+    append_key(key, S_off);
+    append_key(key, ws);
+    return key;
+}
+
+// Limits of the tiled path (LDS of its matching state, graph length).
+cfsim_status check_large_limits(int max_nodes, const cfsim_options* opt) {
+    if (max_nodes > cfsim::kLargeMaxNodes)
+        return fail(CFSIM_E_UNSUPPORTED, "graphs above %d nodes on the tiled path (large pairs, resize)",
+                    cfsim::kLargeMaxNodes);
+    if (opt->max_iter > 4096) return fail(CFSIM_E_UNSUPPORTED, "max_iter above 4096 on the tiled path");
+    return CFSIM_OK;
 }
 
 }  // namespace
@@ -302,6 +417,7 @@ size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t
     (void)ctx;
     if (n_a < 1 || n_b < 1 || !opt) return 0;
     const size_t esize = esize_of(opt->dtype);
+    if (opt->resize == CFSIM_RESIZE_BILINEAR) return large_ws_bytes(1, n_a > n_b ? n_a : n_b, (int)esize, 6);
     // S_{k-2} slot (LDS kernels) or S_cur, S_next, S_{k-2} (global kernel)
     return align256(3 * (size_t)n_a * (size_t)n_b * esize);
 }
@@ -315,6 +431,25 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     if ((s = check_options(opt)) != CFSIM_OK) return s;
     if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
     const int esize = esize_of(opt->dtype);
+    if (opt->resize == CFSIM_RESIZE_BILINEAR) {
+        // scaled pairs run on the tiled path (the resized operator in factored form)
+        const int M = A->n > B->n ? A->n : B->n;
+        if ((s = check_large_limits(M, opt)) != CFSIM_OK) return s;
+        const size_t need = cfsim_score_workspace_size(ctx, A->n, B->n, opt);
+        if (ws_bytes < need || !ws)
+            return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+        cfsim::LargeJob J = large_job(opt, 1, M, res, match_out, nullptr, S_out, nullptr, ws);
+        J.single = 1;
+        J.ga = ref_of(A);
+        J.gb = ref_of(B);
+        int e = (int)hipSetDevice(ctx->device);
+        if (e != 0) return hip_fail(e, "hipSetDevice");
+        e = cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)),
+                                static_cast<hipStream_t>(stream));
+        if (e != 0) return hip_fail(e, "tiled-path launch");
+        return ok();
+    }
     cfsim::PairShape sh;
     const int variant = plain_variant(A->n, B->n, A->nnz, B->nnz, esize, &sh);
     if (variant < 0)
@@ -344,10 +479,11 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
 // ------------------------------------------------------------------ batch (a2-a8)
 size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
                                   const cfsim_options* opt) {
-    (void)ctx;
-    (void)set;
-    (void)opt;
     if (n_pairs < 0 || !set || !opt || set->max_nodes < 1) return 0;
+    if (opt->resize == CFSIM_RESIZE_BILINEAR) {
+        if (set->max_nodes > cfsim::kLargeMaxNodes) return 0;
+        return large_ws_bytes(n_pairs > 0 ? n_pairs : 1, set->max_nodes, esize_of(opt->dtype), 6);
+    }
     return batch_ws_bytes(ctx, n_pairs, esize_of(opt->dtype), set->max_nodes);
 }
 
@@ -407,6 +543,34 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
     return 0;
 }
 
+static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                         hipStream_t st) {
+    cfsim::LargeJob J = large_job(opt, n_pairs, set->max_nodes, res, match, match_off, S_out, S_off, ws);
+    J.set = ref_of(set);
+    J.pair_a = pair_a;
+    J.pair_b = pair_b;
+    return cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)), st);
+}
+
+// The tiled path over the pairs of a set (large pairs; every pair when resized).
+static cfsim_status run_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                              const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                              cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                              const int64_t* S_off, void* ws, hipStream_t st) {
+    if (graphs_disabled()) {
+        const int e = enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws,
+                                    st);
+        if (e != 0) return hip_fail(e, "tiled-path launch");
+        return ok();
+    }
+    const auto key = set_call_key(set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    return replay_or_capture(ctx, &ctx->large_graph, &ctx->large_exec, &ctx->large_key, key, st, [&](hipStream_t cs) {
+        return enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs);
+    });
+}
+
 cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                                const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
                                cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
@@ -423,67 +587,32 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
     if ((S_out == nullptr) != (S_off == nullptr))
         return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
-    const size_t need = batch_ws_bytes(ctx, n_pairs, esize_of(opt->dtype), set->max_nodes);
+    const bool resize = opt->resize == CFSIM_RESIZE_BILINEAR;
+    if (resize && (s = check_large_limits(set->max_nodes, opt)) != CFSIM_OK) return s;
+    const size_t need = cfsim_batch_workspace_size(ctx, set, n_pairs, opt);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     if (n_pairs == 0) return ok();
     int e = (int)hipSetDevice(ctx->device);
     if (e != 0) return hip_fail(e, "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
-
-    const char* nog = getenv("CFSIM_NO_GRAPH");
-    if (ctx->timing || (nog && nog[0] == '1')) {
+    if (resize) {
+        // scaled pairs run on the tiled path (the resized operator in factored form)
+        ctx->timed = 0;
+        return run_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+    }
+    if (ctx->timing || graphs_disabled()) {
         e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st,
                           ctx->timing != 0);
         if (e != 0) return hip_fail(e, "batch launch");
         if (ctx->timing) ctx->timed = 1;
         return ok();
     }
-
-    std::vector<unsigned char> key;
-    append_key(key, *set);
-    append_key(key, pair_a);
-    append_key(key, pair_b);
-    append_key(key, n_pairs);
-    append_key(key, *opt);
-    append_key(key, res);
-    append_key(key, match);
-    append_key(key, match_off);
-    append_key(key, S_out);
-    append_key(key, S_off);
-    append_key(key, ws);
-    if (!ctx->exec || key != ctx->key) {
-        if (ctx->exec) {
-            (void)hipGraphExecDestroy(ctx->exec);
-            ctx->exec = nullptr;
-        }
-        if (ctx->graph) {
-            (void)hipGraphDestroy(ctx->graph);
-            ctx->graph = nullptr;
-        }
-        ctx->key.clear();
-        if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
-            return hip_fail(e, "hipStreamBeginCapture");
-        const int le = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
-                                     ws, ctx->cap, false);
-        hipGraph_t g = nullptr;
-        e = (int)hipStreamEndCapture(ctx->cap, &g);
-        if (le != 0) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(le, "batch launch during capture");
-        }
-        if (e != 0) return hip_fail(e, "hipStreamEndCapture");
-        hipGraphExec_t x = nullptr;
-        if ((e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != 0) {
-            (void)hipGraphDestroy(g);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        ctx->graph = g;
-        ctx->exec = x;
-        ctx->key = key;
-    }
-    if ((e = (int)hipGraphLaunch(ctx->exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
-    return ok();
+    const auto key = set_call_key(set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    return replay_or_capture(ctx, &ctx->graph, &ctx->exec, &ctx->key, key, st, [&](hipStream_t cs) {
+        return enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs,
+                             false);
+    });
 }
 
 cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -497,6 +626,8 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     if (n_pairs > 0 && (!pair_a || !pair_b || !bucket))
         return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or bucket is NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
+    if (opt->resize == CFSIM_RESIZE_BILINEAR)
+        return fail(CFSIM_E_UNSUPPORTED, "resized pairs run on the tiled path, which has no buckets");
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     if (n_pairs == 0) return ok();
     int e = (int)hipSetDevice(ctx->device);
@@ -544,54 +675,11 @@ cfsim_status cfsim_batch_timings(cfsim_context* ctx, float* ms) {
 }
 
 // ------------------------------------------------------------------ large pairs (a9)
-// Workspace: state[n_pairs] | tile_off[n_pairs + 1] | done[n_pairs]
-//   | part_nu, part_delta [n_pairs * large_tiles(max_nodes)] | 4 iterates per pair
-static size_t large_ws_bytes(int64_t n_pairs, int max_nodes, int esize) {
-    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(max_nodes);
-    return align256((size_t)n_pairs * sizeof(cfsim::LargeState)) + align256((size_t)(n_pairs + 1) * 8) +
-           align256((size_t)n_pairs * 4) + 2 * align256(tiles * 8) +
-           (size_t)n_pairs * 4 * (size_t)global_slot_elems(max_nodes) * (size_t)esize;
-}
-
 size_t cfsim_large_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set, int64_t n_pairs,
                                   const cfsim_options* opt) {
     (void)ctx;
     if (n_pairs < 1 || !set || !opt || set->max_nodes < 1 || set->max_nodes > cfsim::kLargeMaxNodes) return 0;
-    return large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype));
-}
-
-static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
-                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
-                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
-                         hipStream_t st) {
-    cfsim::LargeJob J{};
-    J.set = ref_of(set);
-    J.pair_a = pair_a;
-    J.pair_b = pair_b;
-    J.n_pairs = (int)n_pairs;
-    J.max_nodes = set->max_nodes;
-    J.max_iter = opt->max_iter;
-    J.tol = opt->tol;
-    J.res = res;
-    J.match = match;
-    J.match_off = match_off;
-    J.S_out = S_out;
-    J.S_off = S_off;
-    unsigned char* p = static_cast<unsigned char*>(ws);
-    const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(set->max_nodes);
-    J.st = reinterpret_cast<cfsim::LargeState*>(p);
-    p += align256((size_t)n_pairs * sizeof(cfsim::LargeState));
-    J.tile_off = reinterpret_cast<long long*>(p);
-    p += align256((size_t)(n_pairs + 1) * 8);
-    J.done = reinterpret_cast<int*>(p);
-    p += align256((size_t)n_pairs * 4);
-    J.part_nu = reinterpret_cast<double*>(p);
-    p += align256(tiles * 8);
-    J.part_delta = reinterpret_cast<double*>(p);
-    p += align256(tiles * 8);
-    J.bufs = p;
-    J.slot_elems = global_slot_elems(set->max_nodes);
-    return cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)), st);
+    return large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype), large_nslots(opt));
 }
 
 cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -602,76 +690,25 @@ cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set, c
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
     if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
-    if (n_pairs > 65535) return fail(CFSIM_E_UNSUPPORTED, "more than 65535 pairs in one large-pair call");
+    if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
     if (n_pairs > 0 && (!pair_a || !pair_b || !res))
         return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or res is NULL");
     if ((match == nullptr) != (match_off == nullptr))
         return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
     if ((S_out == nullptr) != (S_off == nullptr))
         return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
-    if (set->max_nodes > cfsim::kLargeMaxNodes)
-        return fail(CFSIM_E_UNSUPPORTED, "max_nodes above %d for the large-pair path", cfsim::kLargeMaxNodes);
-    if (opt->max_iter > 4096) return fail(CFSIM_E_UNSUPPORTED, "max_iter above 4096 for the large-pair path");
+    if ((s = check_large_limits(set->max_nodes, opt)) != CFSIM_OK) return s;
     if (n_pairs == 0) {
         if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
         return ok();
     }
-    const size_t need = large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype));
+    const size_t need = cfsim_large_workspace_size(ctx, set, n_pairs, opt);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     int e = (int)hipSetDevice(ctx->device);
     if (e != 0) return hip_fail(e, "hipSetDevice");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const char* nog = getenv("CFSIM_NO_GRAPH");
-    if (nog && nog[0] == '1') {
-        e = enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
-        if (e != 0) return hip_fail(e, "large-pair launch");
-        return ok();
-    }
-    std::vector<unsigned char> key;
-    append_key(key, *set);
-    append_key(key, pair_a);
-    append_key(key, pair_b);
-    append_key(key, n_pairs);
-    append_key(key, *opt);
-    append_key(key, res);
-    append_key(key, match);
-    append_key(key, match_off);
-    append_key(key, S_out);
-    append_key(key, S_off);
-    append_key(key, ws);
-    if (!ctx->large_exec || key != ctx->large_key) {
-        if (ctx->large_exec) {
-            (void)hipGraphExecDestroy(ctx->large_exec);
-            ctx->large_exec = nullptr;
-        }
-        if (ctx->large_graph) {
-            (void)hipGraphDestroy(ctx->large_graph);
-            ctx->large_graph = nullptr;
-        }
-        ctx->large_key.clear();
-        if ((e = (int)hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal)) != 0)
-            return hip_fail(e, "hipStreamBeginCapture");
-        const int le =
-            enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, ctx->cap);
-        hipGraph_t g = nullptr;
-        e = (int)hipStreamEndCapture(ctx->cap, &g);
-        if (le != 0) {
-            if (g) (void)hipGraphDestroy(g);
-            return hip_fail(le, "large-pair launch during capture");
-        }
-        if (e != 0) return hip_fail(e, "hipStreamEndCapture");
-        hipGraphExec_t x = nullptr;
-        if ((e = (int)hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != 0) {
-            (void)hipGraphDestroy(g);
-            return hip_fail(e, "hipGraphInstantiate");
-        }
-        ctx->large_graph = g;
-        ctx->large_exec = x;
-        ctx->large_key = key;
-    }
-    if ((e = (int)hipGraphLaunch(ctx->large_exec, st)) != 0) return hip_fail(e, "hipGraphLaunch");
-    return ok();
+    return run_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws,
+                     static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------------------ adjoint (a10)
@@ -695,6 +732,8 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
     if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
     if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
     if (checkpoint_every < 1) return fail(CFSIM_E_INVALID_ARG, "checkpoint_every must be >= 1");
+    if (opt->resize == CFSIM_RESIZE_BILINEAR)
+        return fail(CFSIM_E_UNSUPPORTED, "the reverse mode runs on the unscaled operator only");
     if (n_pairs > 0 && (!pair_a || !pair_b || !fwd || !match || !match_off || !grad_score || !grad_w))
         return fail(CFSIM_E_INVALID_ARG, "a pair, forward-result, matching or gradient array is NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");

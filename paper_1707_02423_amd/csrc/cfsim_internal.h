@@ -245,7 +245,11 @@ int launch_pack(const PackJob& job, hipStream_t stream);
 // Large pairs (large.hip): per-pair state and the launch descriptor.
 struct LargeState {
     int nA, nB;
-    int ntiles;          // tiles of Y (32 rows x 64 columns)
+    int rz;              // scaled to a common size (resize requested and n_A != n_B)
+    int swap;            // state rows are A's nodes (rows = B's otherwise)
+    int nR, nC;          // state shape: n_B x n_A, or M x m when resized
+    int M;               // common size when resized
+    int ntiles;          // tiles of the state (32 rows x 64 columns)
     int active;          // still iterating
     unsigned status;     // CFSIM_* bits once decided
     int final_step;      // k of the returned iterate
@@ -254,6 +258,8 @@ struct LargeState {
 };
 
 struct LargeJob {
+    int single;          // one explicit pair (ga, gb) instead of pairs of a set
+    GraphRef ga, gb;
     SetRef set;
     const int32_t* pair_a;
     const int32_t* pair_b;
@@ -261,6 +267,7 @@ struct LargeJob {
     int max_nodes;
     int max_iter;
     double tol;
+    int resize;          // CFSIM_RESIZE_BILINEAR
     cfsim_pair_result* res;
     int32_t* match;
     const int64_t* match_off;
@@ -272,7 +279,8 @@ struct LargeJob {
     int* done;           // [n_pairs] tiles finished in the current launch
     double* part_nu;     // [tiles] squared-norm partials of Y
     double* part_delta;  // [tiles] squared partials of S_{k-1} - S_{k-3}
-    void* bufs;          // [n_pairs][4][slot_elems] rotating iterates
+    void* bufs;          // [n_pairs][nslots][slot_elems]: 4 rotating iterates (+ V, S when resized)
+    int nslots;
     long long slot_elems;
 };
 

@@ -1,19 +1,30 @@
-// Step a9: large pairs (hundreds to thousands of nodes per graph).
+// Step a9 (large pairs) and step a2 (scale to a common size) on the tiled,
+// global-memory path.
 //
 // S no longer fits a workgroup's LDS, so every update is one grid-wide launch
-// over tiles of all pairs of the call, with S in HBM (the MI355X last-level
-// cache holds a pair's working set).  The host captures the sequence
-//   large_init, large_scan, large_step(k) for k = 1 .. max_iter + 1, large_finish
-// into one HIP graph.  Per pair four buffers rotate: launch k reads
-// Y_{k-1} (with the scale sigma_{k-1} = 1 / nu_{k-1} folded into the update,
-// so no separate normalisation pass runs) and writes the un-normalised
-// Y_k = M S_{k-1}.  The even-step change delta_{k-1} = ||S_{k-1} - S_{k-3}||
-// is accumulated by the odd launch k, which is the first one that knows both
-// scales.  The last workgroup to finish a pair's tiles in a launch (counted
-// with a device-scope atomic) reduces the pair's per-tile FP64 partials in
-// tile order, so the reductions are deterministic.  Launch max_iter + 1 only
-// computes the final even-step change.  large_finish rescales the final
-// iterate in place and runs the greedy matching with one workgroup per pair.
+// over tiles of all pairs of the call, with the iterates in HBM (the MI355X
+// last-level cache holds a pair's working set).  The host captures the whole
+// sequence into one HIP graph.  The last workgroup to finish a pair's tiles in
+// a launch (counted with a device-scope atomic) reduces the pair's per-tile
+// FP64 partials in tile order, so every reduction is deterministic.
+//
+// Plain operator (no resize): four buffers rotate per pair; launch k reads
+// Y_{k-1} with sigma_{k-1} = 1/nu_{k-1} folded into the update and writes the
+// un-normalised Y_k = M S_{k-1}.  The even-step change
+// delta_{k-1} = ||S_{k-1} - S_{k-3}|| is accumulated by the odd launch k, the
+// first one that knows both scales; launch max_iter + 1 only does that.
+//
+// Scale to a common size (Section 3, Section 3.1): the smaller graph X (m
+// nodes) is replaced by X' = R X R^T with the M x m linear-interpolation
+// matrix R.  X' is never formed.  With the small graph on the column side,
+//   Y = Rg S Cg'^T + Rg^T S Cg' = [Rg (S R) Cg^T + Rg^T (S R) Cg] R^T,
+// so the iteration carries U = M_{Rg,Cg}(S R) (M x m, the plain operator at
+// the small size) and V = U G with the tridiagonal G = R^T R:
+//   U_k = M(V_{k-1}) / nu_{k-1},  V_k = U_k G,  nu_k^2 = <U_k, V_k> = ||Y_k||^2,
+//   delta_k^2 = <D, D G> with D = U_k / nu_k - U_{k-2} / nu_{k-2},
+// and S_k = U_k R^T / nu_k is expanded once at the end.  S_0 = 1/M is
+// U_0 = 1/M (every row of R sums to 1).  Each update is then two launches:
+// large_step (U) and large_gram (V, the norms and the stopping decision).
 #include "cfsim_internal.h"
 #include "pair_device.h"
 
@@ -26,20 +37,24 @@ using dev::uni;
 using dev::wave_argmax;
 using dev::wave_sum;
 
-constexpr int kTileRows = 32;                   // rows of Y per tile
+constexpr int kTileRows = 32;                   // rows per tile
 constexpr int kStepThreads = 256;               // 4 waves, 8 rows each
-constexpr int kRowsPerWave = kTileRows / (kStepThreads / kWave);
+constexpr int kNWStep = kStepThreads / kWave;
+constexpr int kRowsPerWave = kTileRows / kNWStep;
 constexpr int kFinishThreads = 1024;
 constexpr int kLS = 2;                          // successors per lane column in registers
 constexpr int kLP = 3;                          // predecessors per lane column in registers
+constexpr int kSlotU = 0;                       // resize: U_k in slot k % 4
+constexpr int kSlotV = 4;                       // resize: V
+constexpr int kSlotS = 5;                       // resize: expanded final S
 
-__device__ inline int tiles_of(int nA, int nB) { return ((nB + kTileRows - 1) / kTileRows) * ((nA + 63) / 64); }
+__device__ inline int tiles_of(int nC, int nR) { return ((nR + kTileRows - 1) / kTileRows) * ((nC + 63) / 64); }
 static_assert(kTileRows == 32, "large_tiles() in cfsim_internal.h assumes 32-row tiles");
 
-// Pair p's buffer b (0..3) of slot_elems elements.
+// Pair p's buffer b of slot_elems elements.
 template <typename T>
 __device__ inline T* buf_of(const LargeJob& J, int p, int b) {
-    return reinterpret_cast<T*>(J.bufs) + ((long long)p * 4 + b) * J.slot_elems;
+    return reinterpret_cast<T*>(J.bufs) + ((long long)p * J.nslots + b) * J.slot_elems;
 }
 
 __device__ inline int pair_of_tile(const LargeJob& J, long long t) {
@@ -51,24 +66,97 @@ __device__ inline int pair_of_tile(const LargeJob& J, long long t) {
     return lo;
 }
 
+__device__ inline bool pair_graphs(const LargeJob& J, int p, GraphRef* A, GraphRef* B) {
+    if (J.single) {
+        *A = J.ga;
+        *B = J.gb;
+        return true;
+    }
+    const int ga = J.pair_a[p], gb = J.pair_b[p];
+    if (ga < 0 || ga >= J.set.n_graphs || gb < 0 || gb >= J.set.n_graphs) return false;
+    *A = graph_of(J.set, ga);
+    *B = graph_of(J.set, gb);
+    return true;
+}
+
+// Row graph (wave-uniform rows) and column graph (lanes) of the state.
+__device__ inline void state_graphs(const LargeJob& J, int p, const LargeState* s, GraphRef* Rg, GraphRef* Cg) {
+    GraphRef A, B;
+    pair_graphs(J, p, &A, &B);
+    *Rg = s->swap ? A : B;
+    *Cg = s->swap ? B : A;
+}
+
+// Interpolation from m to M points at p (m - 1) / (M - 1): row p of R holds
+// 1 - f at column r0 and f at column r1 (one entry 1 when r0 = r1).
+struct Interp {
+    int r0, r1;
+    double f;
+};
+__device__ inline Interp interp_at(int p, int m, int M) {
+    Interp q;
+    if (M <= 1) {
+        q.r0 = q.r1 = 0;
+        q.f = 0.0;
+        return q;
+    }
+    const long long num = (long long)p * (m - 1);
+    q.r0 = (int)(num / (M - 1));
+    q.f = (double)(num - (long long)q.r0 * (M - 1)) / (double)(M - 1);
+    q.r1 = q.r0 + 1 < m ? q.r0 + 1 : m - 1;
+    return q;
+}
+
+// First and last p with r0(p) = u.
+__device__ inline void interp_rows(int u, int m, int M, int* plo, int* phi) {
+    if (m <= 1) {
+        *plo = 0;
+        *phi = M - 1;
+        return;
+    }
+    const long long a = (long long)u * (M - 1), b = (long long)(u + 1) * (M - 1);
+    *plo = (int)((a + (m - 2)) / (m - 1));
+    *phi = u == m - 1 ? M - 1 : (int)((b + (m - 2)) / (m - 1)) - 1;
+}
+
+// G = R^T R at column u: diagonal d and the coupling e = G[u][u+1].
+__device__ inline void gram_entries(int u, int m, int M, double* d, double* e) {
+    double dd = 0.0, ee = 0.0;
+    int lo, hi;
+    interp_rows(u, m, M, &lo, &hi);
+    for (int p = lo; p <= hi; ++p) {
+        const Interp q = interp_at(p, m, M);
+        if (q.r1 == q.r0) {
+            dd += 1.0;  // (1 - f + f)^2 with a single entry
+        } else {
+            dd += (1.0 - q.f) * (1.0 - q.f);
+            ee += (1.0 - q.f) * q.f;
+        }
+    }
+    if (u > 0) {
+        interp_rows(u - 1, m, M, &lo, &hi);
+        for (int p = lo; p <= hi; ++p) {
+            const Interp q = interp_at(p, m, M);
+            if (q.r1 == u && q.r0 != q.r1) dd += q.f * q.f;
+        }
+    }
+    *d = dd;
+    *e = ee;
+}
+
 // ---------------------------------------------------------------- set-up
-// One workgroup per pair: validity, degeneracy, tile count, initial state.
+// One workgroup per pair: validity, degeneracy, state shape, initial state.
 __global__ __launch_bounds__(256) void large_init(LargeJob J) {
     const int p = blockIdx.x;
     __shared__ int pos[2];
-    const int ga = J.pair_a[p], gb = J.pair_b[p];
     LargeState* s = J.st + p;
-    const bool ok_ids = ga >= 0 && ga < J.set.n_graphs && gb >= 0 && gb < J.set.n_graphs;
-    int nA = 0, nB = 0;
     GraphRef A{}, B{};
-    if (ok_ids) {
-        A = graph_of(J.set, ga);
-        B = graph_of(J.set, gb);
-        nA = A.n;
-        nB = B.n;
-    }
-    const bool ok = ok_ids && nA >= 1 && nB >= 1 && (long long)nA * nB <= J.slot_elems && nA <= J.max_nodes &&
-                    nB <= J.max_nodes;
+    const bool ok_ids = pair_graphs(J, p, &A, &B);
+    const int nA = ok_ids ? A.n : 0, nB = ok_ids ? B.n : 0;
+    const int M = nA > nB ? nA : nB;
+    const bool rz = J.resize && nA != nB;
+    const bool ok = ok_ids && nA >= 1 && nB >= 1 && nA <= J.max_nodes && nB <= J.max_nodes &&
+                    (long long)(rz ? M : nA) * (rz ? M : nB) <= J.slot_elems;
     if (threadIdx.x < 2) pos[threadIdx.x] = 0;
     __syncthreads();
     if (ok) {
@@ -81,7 +169,12 @@ __global__ __launch_bounds__(256) void large_init(LargeJob J) {
     if (threadIdx.x == 0) {
         s->nA = nA;
         s->nB = nB;
-        s->ntiles = ok ? tiles_of(nA, nB) : 0;
+        s->rz = rz ? 1 : 0;
+        s->swap = rz && nB < nA ? 1 : 0;  // the smaller graph takes the column side
+        s->nR = rz ? M : nB;
+        s->nC = rz ? (nA < nB ? nA : nB) : nA;
+        s->M = rz ? M : 0;
+        s->ntiles = ok ? tiles_of(s->nC, s->nR) : 0;
         s->active = (ok && pos[0] && pos[1]) ? 1 : 0;
         s->status = !ok ? CFSIM_INVALID_INPUT : (s->active ? 0u : (unsigned)CFSIM_DEGENERATE);
         s->final_step = 0;
@@ -119,202 +212,318 @@ __global__ __launch_bounds__(1024) void large_scan(LargeJob J) {
     }
 }
 
-// ---------------------------------------------------------------- one update
-// Launch k (1 .. max_iter): Y_k = M (Y_{k-1} / nu_{k-1}) into buffer k % 4
-// (S_0 is the constant 1/sqrt(n_A n_B)); at odd k >= 3 also the partial
-// squares of S_{k-1} - S_{k-3}.  Launch max_iter + 1 computes only the latter.
+// ---------------------------------------------------------------- tiles
+struct Tile {
+    int r0, c0;
+};
+
+// XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
+// the workgroups of one XCD take one contiguous range of tiles (neighbouring
+// row strips of one pair share rows of the iterate through that XCD's L2).
+struct TileRange {
+    long long first, end, stride;
+};
+__device__ inline TileRange tile_range(const LargeJob& J) {
+    const long long total = J.tile_off[J.n_pairs];
+    const int xcd = blockIdx.x & 7, y = blockIdx.x >> 3;
+    TileRange r;
+    r.first = total * xcd / 8 + y;
+    r.end = total * (xcd + 1) / 8;
+    r.stride = gridDim.x >> 3;
+    return r;
+}
+
+__device__ inline Tile tile_at(const LargeJob& J, long long t, const LargeState* s, int p) {
+    Tile x;
+    const int lt = (int)(t - J.tile_off[p]);
+    const int nct = (s->nC + 63) / 64;
+    x.r0 = (lt / nct) * kTileRows;
+    x.c0 = (lt % nct) * 64;
+    return x;
+}
+
+// Reduce the per-tile partials of pair p (called by the workgroup that
+// finished the pair's last tile of this launch) and decide whether the pair
+// stops.  k: launch index; compute: a new iterate was formed; want_delta:
+// the partials of delta_{k-1} were accumulated.
+__device__ void reduce_and_decide(const LargeJob& J, int p, int k, bool compute, bool want_delta, double* red) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    LargeState* s = J.st + p;
+    __threadfence();
+    const long long t0 = J.tile_off[p], nt = s->ntiles;
+    double a = 0.0, b = 0.0;
+    for (long long q = tid; q < nt; q += kStepThreads) {
+        a += J.part_nu[t0 + q];
+        b += J.part_delta[t0 + q];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        red[wave] = a;
+        red[kNWStep + wave] = b;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double nu2s = 0.0, d2s = 0.0;
+        for (int w = 0; w < kNWStep; ++w) {
+            nu2s += red[w];
+            d2s += red[kNWStep + w];
+        }
+        J.done[p] = 0;
+        bool stop = false;
+        if (want_delta) {
+            const double delta = sqrt(d2s);
+            s->delta = delta;
+            if (delta < J.tol) {   // converged at the even step k - 1
+                s->final_step = k - 1;
+                s->nu = s->nu_k[(k - 1) & 3];
+                s->status = CFSIM_CONVERGED;
+                stop = true;
+            }
+        }
+        if (!stop && compute) {
+            const double nu = sqrt(nu2s);
+            s->nu_k[k & 3] = nu;
+            if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
+                s->final_step = k;
+                s->nu = nu;
+                s->status = CFSIM_HIT_MAX_ITER;
+                stop = true;
+            }
+        }
+        if (!stop && !compute) {               // launch max_iter + 1
+            s->final_step = J.max_iter;
+            s->nu = s->nu_k[J.max_iter & 3];
+            s->status = CFSIM_HIT_MAX_ITER;
+            stop = true;
+        }
+        if (stop) s->active = 0;
+    }
+}
+
+// Per-tile partials (fixed order: waves, then lanes), then the pair's last
+// tile of this launch reduces them.
+__device__ void tile_partials(const LargeJob& J, long long t, int p, int k, bool compute, bool want_delta,
+                              double nu2, double d2, double* red, int* last_flag) {
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    nu2 = wave_sum(nu2);
+    d2 = wave_sum(d2);
+    if (lane == 0) {
+        red[wave] = nu2;
+        red[kNWStep + wave] = d2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < kNWStep; ++w) {
+            a += red[w];
+            b += red[kNWStep + w];
+        }
+        J.part_nu[t] = a;
+        J.part_delta[t] = b;
+        __threadfence();
+        const int prev = atomicAdd(J.done + p, 1);
+        *last_flag = prev == J.st[p].ntiles - 1;
+    }
+    __syncthreads();
+    if (*last_flag) reduce_and_decide(J, p, k, compute, want_delta, red);
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- the operator
+// Launch k (1 .. max_iter): X_k = M_{Rg,Cg}(src) * sigma_{k-1} over the state
+// (nR x nC).  Plain pairs: src = Y_{k-1} (S_0 is the constant
+// 1/sqrt(n_A n_B)), X_k = Y_k into buffer k % 4, plus the norm partials and,
+// at odd k >= 3, those of S_{k-1} - S_{k-3}.  Resized pairs: src = V_{k-1},
+// X_k = U_k into slot k % 4; large_gram does the rest.  Launch max_iter + 1
+// computes only the last change of plain pairs.
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
-    __shared__ double red[2][kStepThreads / kWave];
+    __shared__ double red[2 * kNWStep];
     __shared__ int last_flag;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const bool compute = k <= J.max_iter;
     const bool want_delta = (k & 1) && k >= 3;
-    const long long total = J.tile_off[J.n_pairs];
-    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so the
-    // workgroups of one XCD take one contiguous range of tiles (neighbouring
-    // row strips of one pair share S rows through that XCD's L2).
-    const int G = gridDim.x;
-    const int xcd = blockIdx.x & 7, per_xcd = G >> 3, y = blockIdx.x >> 3;
-    const long long lo = total * xcd / 8, hi = total * (xcd + 1) / 8;
-    for (long long t = lo + y; t < hi; t += per_xcd) {
+    const TileRange tr = tile_range(J);
+    for (long long t = tr.first; t < tr.end; t += tr.stride) {
         const int p = uni(pair_of_tile(J, t));
         LargeState* s = J.st + p;
         if (!uni(s->active)) continue;
-        const int nA = s->nA, nB = s->nB;
-        const int lt = (int)(t - J.tile_off[p]);
-        const int nct = (nA + 63) / 64;
-        const int r0 = (lt / nct) * kTileRows, c0 = (lt % nct) * 64;
-        const GraphRef A = graph_of(J.set, J.pair_a[p]);
-        const GraphRef B = graph_of(J.set, J.pair_b[p]);
-        const int j = c0 + lane;
-        const bool colv = j < nA;
-        const T* src = buf_of<T>(J, p, (k - 1) & 3);
+        const bool rz = uni(s->rz) != 0;
+        if (rz && !compute) continue;
+        const Tile tl = tile_at(J, t, s, p);
+        const int nR = s->nR, nC = s->nC;
+        GraphRef Rg, Cg;
+        state_graphs(J, p, s, &Rg, &Cg);
+        const int j = tl.c0 + lane;
+        const bool colv = j < nC;
+        const T* src = rz ? buf_of<T>(J, p, kSlotV) : buf_of<T>(J, p, (k - 1) & 3);
         T* dst = buf_of<T>(J, p, k & 3);
         const T* old = buf_of<T>(J, p, (k - 3) & 3);
-        const T c0v = T(1.0 / sqrt((double)nA * (double)nB));
+        const T c0v = T(1.0 / sqrt((double)s->nA * (double)s->nB));
         const T sig = T(1.0 / s->nu_k[(k - 1) & 3]);     // sigma_{k-1} (1 for S_0)
         const T sig3 = T(1.0 / s->nu_k[(k - 3) & 3]);    // sigma_{k-3}
-        const bool first = k == 1;                        // S_0 is the constant
+        const bool first = k == 1 && !rz;                 // S_0 is the constant
         const bool old_is_s0 = k == 3;
-        // the lane column's neighbour lists in A (padding has zero weight)
+        // the lane column's neighbour lists in Cg (padding has zero weight)
         int sv[kLS], pv[kLP];
         T sw[kLS], pw[kLP];
         int ns = 0, np = 0, sb = 0, pb = 0;
         if (colv) {
-            sb = A.rp[j];
-            ns = A.rp[j + 1] - sb;
-            pb = A.cp[j];
-            np = A.cp[j + 1] - pb;
+            sb = Cg.rp[j];
+            ns = Cg.rp[j + 1] - sb;
+            pb = Cg.cp[j];
+            np = Cg.cp[j + 1] - pb;
         }
 #pragma unroll
         for (int q = 0; q < kLS; ++q) {
-            sv[q] = q < ns ? A.ci[sb + q] : 0;
-            sw[q] = q < ns ? T(A.w[sb + q]) : T(0);
+            sv[q] = q < ns ? Cg.ci[sb + q] : 0;
+            sw[q] = q < ns ? T(Cg.w[sb + q]) : T(0);
         }
 #pragma unroll
         for (int q = 0; q < kLP; ++q) {
-            pv[q] = q < np ? A.ri[pb + q] : 0;
-            pw[q] = q < np ? T(A.w[A.eid[pb + q]]) : T(0);
+            pv[q] = q < np ? Cg.ri[pb + q] : 0;
+            pw[q] = q < np ? T(Cg.w[Cg.eid[pb + q]]) : T(0);
         }
         const bool ovf = uni(dev::wave_max(max(ns - kLS, np - kLP))) > 0;
         double nu2 = 0.0, d2 = 0.0;
         for (int rr = 0; rr < kRowsPerWave; ++rr) {
-            const int i = r0 + wave * kRowsPerWave + rr;
-            if (i >= nB) break;
+            const int i = tl.r0 + wave * kRowsPerWave + rr;
+            if (i >= nR) break;
             if (compute) {
                 T acc = T(0);
                 if (first) {
-                    // S_0 constant: Y_1[i][j] = c0 (outdeg_w_B(i) outdeg_w_A(j) + indeg_w_B(i) indeg_w_A(j))
+                    // S_0 constant: Y_1[i][j] = c0 (outw_Rg(i) outw_Cg(j) + inw_Rg(i) inw_Cg(j))
                     T ra = T(0), rb = T(0), qa = T(0), qb = T(0);
-                    for (int e = 0; e < ns; ++e) ra += T(A.w[sb + e]);
-                    for (int e = 0; e < np; ++e) qa += T(A.w[A.eid[pb + e]]);
-                    for (int e = B.rp[i]; e < B.rp[i + 1]; ++e) rb += T(B.w[e]);
-                    for (int e = B.cp[i]; e < B.cp[i + 1]; ++e) qb += T(B.w[B.eid[e]]);
+                    for (int e = 0; e < ns; ++e) ra += T(Cg.w[sb + e]);
+                    for (int e = 0; e < np; ++e) qa += T(Cg.w[Cg.eid[pb + e]]);
+                    for (int e = Rg.rp[i]; e < Rg.rp[i + 1]; ++e) rb += T(Rg.w[e]);
+                    for (int e = Rg.cp[i]; e < Rg.cp[i + 1]; ++e) qb += T(Rg.w[Rg.eid[e]]);
                     acc = c0v * (rb * ra + qb * qa);
                 } else {
-                    const int e1 = uni(B.rp[i + 1]);
-                    for (int e = uni(B.rp[i]); e < e1; ++e) {
-                        const int u = uni(B.ci[e]);
-                        const T wu = T(B.w[e]);
-                        const T* row = src + (long long)u * nA;
+                    const int e1 = uni(Rg.rp[i + 1]);
+                    for (int e = uni(Rg.rp[i]); e < e1; ++e) {
+                        const int u = uni(Rg.ci[e]);
+                        const T wu = T(Rg.w[e]);
+                        const T* row = src + (long long)u * nC;
                         T in = T(0);
 #pragma unroll
                         for (int q = 0; q < kLS; ++q) in = dev::fma_t(sw[q], row[sv[q]], in);
                         if (ovf)
-                            for (int q = kLS; q < ns; ++q) in = dev::fma_t(T(A.w[sb + q]), row[A.ci[sb + q]], in);
+                            for (int q = kLS; q < ns; ++q) in = dev::fma_t(T(Cg.w[sb + q]), row[Cg.ci[sb + q]], in);
                         acc = dev::fma_t(wu, in, acc);
                     }
-                    const int f1 = uni(B.cp[i + 1]);
-                    for (int e = uni(B.cp[i]); e < f1; ++e) {
-                        const int u = uni(B.ri[e]);
-                        const T wu = T(B.w[uni(B.eid[e])]);
-                        const T* row = src + (long long)u * nA;
+                    const int f1 = uni(Rg.cp[i + 1]);
+                    for (int e = uni(Rg.cp[i]); e < f1; ++e) {
+                        const int u = uni(Rg.ri[e]);
+                        const T wu = T(Rg.w[uni(Rg.eid[e])]);
+                        const T* row = src + (long long)u * nC;
                         T in = T(0);
 #pragma unroll
                         for (int q = 0; q < kLP; ++q) in = dev::fma_t(pw[q], row[pv[q]], in);
                         if (ovf)
                             for (int q = kLP; q < np; ++q)
-                                in = dev::fma_t(T(A.w[A.eid[pb + q]]), row[A.ri[pb + q]], in);
+                                in = dev::fma_t(T(Cg.w[Cg.eid[pb + q]]), row[Cg.ri[pb + q]], in);
                         acc = dev::fma_t(wu, in, acc);
                     }
                     acc *= sig;
                 }
                 if (colv) {
-                    dst[(long long)i * nA + j] = acc;
+                    dst[(long long)i * nC + j] = acc;
                     nu2 += (double)acc * (double)acc;
                 }
             }
-            if (want_delta && colv) {
-                const long long o = (long long)i * nA + j;
+            if (!rz && want_delta && colv) {
+                const long long o = (long long)i * nC + j;
                 const T a = T(src[o] * sig);                        // S_{k-1}
                 const T b = old_is_s0 ? c0v : T(old[o] * sig3);     // S_{k-3}
                 const double d = (double)a - (double)b;
                 d2 += d * d;
             }
         }
-        // per-tile partials (fixed order: waves, then lanes)
-        nu2 = wave_sum(nu2);
-        d2 = wave_sum(d2);
-        if (lane == 0) {
-            red[0][wave] = nu2;
-            red[1][wave] = d2;
+        if (rz) continue;   // norms of resized pairs come from large_gram
+        tile_partials(J, t, p, k, compute, want_delta, nu2, d2, red, &last_flag);
+    }
+}
+
+// ---------------------------------------------------------------- resize: G, norms
+// Launch k (0 .. max_iter + 1) for resized pairs: V_k = U_k G (k <= max_iter;
+// U_0 is the constant 1/M), nu_k^2 = <U_k, V_k> (k >= 1), and at odd k >= 3
+// delta_{k-1}^2 = <D, D G>, D = U_{k-1} sigma_{k-1} - U_{k-3} sigma_{k-3}.
+template <typename T>
+__global__ __launch_bounds__(kStepThreads) void large_gram(LargeJob J, int k) {
+    __shared__ double red[2 * kNWStep];
+    __shared__ int last_flag;
+    __shared__ double gd[66], ge[66];  // G diagonal and coupling for columns c0 - 1 .. c0 + 64
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const bool compute = k <= J.max_iter;
+    const bool want_delta = (k & 1) && k >= 3;
+    const TileRange tr = tile_range(J);
+    for (long long t = tr.first; t < tr.end; t += tr.stride) {
+        const int p = uni(pair_of_tile(J, t));
+        LargeState* s = J.st + p;
+        if (!uni(s->active) || !uni(s->rz)) continue;
+        const Tile tl = tile_at(J, t, s, p);
+        const int nR = s->nR, m = s->nC, M = s->M;
+        __syncthreads();
+        for (int q = tid; q < 66; q += kStepThreads) {
+            const int u = tl.c0 - 1 + q;
+            double d = 0.0, e = 0.0;
+            if (u >= 0 && u < m) gram_entries(u, m, M, &d, &e);
+            gd[q] = d;
+            ge[q] = u >= 0 && u + 1 < m ? e : 0.0;
         }
         __syncthreads();
-        if (tid == 0) {
-            double a = 0.0, b = 0.0;
-            for (int w = 0; w < kStepThreads / kWave; ++w) {
-                a += red[0][w];
-                b += red[1][w];
+        const int j = tl.c0 + lane;
+        const bool colv = j < m;
+        const int q = lane + 1;  // index of column j in gd/ge
+        const double g_l = ge[q - 1], g_d = gd[q], g_r = ge[q];  // G[j][j-1], G[j][j], G[j][j+1]
+        const double c0 = 1.0 / (double)M;
+        const T* U = buf_of<T>(J, p, kSlotU + (k & 3));
+        const T* U1 = buf_of<T>(J, p, kSlotU + ((k - 1) & 3));
+        const T* U3 = buf_of<T>(J, p, kSlotU + ((k - 3) & 3));
+        T* V = buf_of<T>(J, p, kSlotV);
+        const double sig1 = 1.0 / s->nu_k[(k - 1) & 3], sig3 = 1.0 / s->nu_k[(k - 3) & 3];
+        double nu2 = 0.0, d2 = 0.0;
+        for (int rr = 0; rr < kRowsPerWave; ++rr) {
+            const int i = tl.r0 + wave * kRowsPerWave + rr;
+            if (i >= nR || !colv) break;
+            const long long o = (long long)i * m + j;
+            if (compute) {
+                double ul, uc, ur;
+                if (k == 0) {
+                    ul = uc = ur = c0;
+                } else {
+                    uc = (double)U[o];
+                    ul = j > 0 ? (double)U[o - 1] : 0.0;
+                    ur = j + 1 < m ? (double)U[o + 1] : 0.0;
+                }
+                const double v = g_l * ul + g_d * uc + g_r * ur;
+                V[o] = T(v);
+                if (k >= 1) nu2 += uc * v;
             }
-            J.part_nu[t] = a;
-            J.part_delta[t] = b;
-            __threadfence();
-            const int prev = atomicAdd(J.done + p, 1);
-            last_flag = prev == s->ntiles - 1;
-        }
-        __syncthreads();
-        if (last_flag) {
-            // the pair's last tile of this launch: reduce its partials in tile order
-            __threadfence();
-            const long long t0 = J.tile_off[p], nt = s->ntiles;
-            double a = 0.0, b = 0.0;
-            for (long long q = tid; q < nt; q += kStepThreads) {
-                a += J.part_nu[t0 + q];
-                b += J.part_delta[t0 + q];
-            }
-            a = wave_sum(a);
-            b = wave_sum(b);
-            __syncthreads();
-            if (lane == 0) {
-                red[0][wave] = a;
-                red[1][wave] = b;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                double nu2s = 0.0, d2s = 0.0;
-                for (int w = 0; w < kStepThreads / kWave; ++w) {
-                    nu2s += red[0][w];
-                    d2s += red[1][w];
-                }
-                J.done[p] = 0;
-                bool stop = false;
-                if (want_delta) {
-                    const double delta = sqrt(d2s);
-                    s->delta = delta;
-                    if (delta < J.tol) {   // converged at the even step k - 1
-                        s->final_step = k - 1;
-                        s->nu = s->nu_k[(k - 1) & 3];
-                        s->status = CFSIM_CONVERGED;
-                        stop = true;
-                    }
-                }
-                if (!stop && compute) {
-                    const double nu = sqrt(nu2s);
-                    s->nu_k[k & 3] = nu;
-                    if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
-                        s->final_step = k;
-                        s->nu = nu;
-                        s->status = CFSIM_HIT_MAX_ITER;
-                        stop = true;
-                    }
-                }
-                if (!stop && !compute) {               // launch max_iter + 1
-                    s->final_step = J.max_iter;
-                    s->nu = s->nu_k[J.max_iter & 3];
-                    s->status = CFSIM_HIT_MAX_ITER;
-                    stop = true;
-                }
-                if (stop) s->active = 0;
+            if (want_delta) {
+                auto dval = [&](long long oo) {
+                    const double a = (double)U1[oo] * sig1;
+                    const double b = k == 3 ? c0 : (double)U3[oo] * sig3;
+                    return a - b;
+                };
+                const double dc = dval(o);
+                const double dl = j > 0 ? dval(o - 1) : 0.0;
+                const double dr = j + 1 < m ? dval(o + 1) : 0.0;
+                d2 += dc * (g_l * dl + g_d * dc + g_r * dr);
             }
         }
-        __syncthreads();
+        if (k == 0) continue;
+        tile_partials(J, t, p, k, compute, want_delta, nu2, d2, red, &last_flag);
     }
 }
 
 // ---------------------------------------------------------------- finish
-// One workgroup per pair: rescale the final iterate in place (S_f = Y_f /
-// nu_f, or S_0 for a degenerate pair), greedy matching, outputs.
+// One workgroup per pair: form the final S (Y_f / nu_f; for a resized pair
+// the expansion U_f R^T / nu_f to M x M; S_0 for a degenerate pair), greedy
+// matching, outputs.
 template <typename T>
 __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -329,16 +538,38 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
         if (tid == 0) dev::write_invalid(res);
         return;
     }
-    const int nA = s->nA, nB = s->nB;
     const int f = s->final_step;
-    T* S = buf_of<T>(J, p, f & 3);
-    const long long total = (long long)nA * nB;
+    const bool rz = s->rz != 0;
+    const int nR = rz ? s->M : s->nB;   // rows of S (B side)
+    const int nC = rz ? s->M : s->nA;   // columns of S (A side)
+    const long long total = (long long)nR * nC;
+    T* S = rz ? buf_of<T>(J, p, kSlotS) : buf_of<T>(J, p, f & 3);
     if (f == 0) {
-        const T c0v = T(1.0 / sqrt((double)nA * (double)nB));
+        const T c0v = T(1.0 / sqrt((double)nR * (double)nC));
         for (long long o = tid; o < total; o += kFinishThreads) S[o] = c0v;
-    } else {
+    } else if (!rz) {
         const T sig = T(1.0 / s->nu_k[f & 3]);
         for (long long o = tid; o < total; o += kFinishThreads) S[o] = S[o] * sig;
+    } else {
+        // state row r (node of the larger graph), expanded column qq; the
+        // state holds S (swap = 0) or S^T (swap = 1)
+        const double sig = 1.0 / s->nu_k[f & 3];
+        const T* U = buf_of<T>(J, p, kSlotU + (f & 3));
+        const int m = s->nC, M = s->M;
+        for (long long o = tid; o < total; o += kFinishThreads) {
+            const int r = (int)(o / M), qq = (int)(o - (long long)r * M);
+            const Interp ip = interp_at(qq, m, M);
+            const T* urow = U + (long long)r * m;
+            double y;
+            if (ip.r1 == ip.r0)
+                y = (double)urow[ip.r0] * sig;
+            else
+                y = (1.0 - ip.f) * ((double)urow[ip.r0] * sig) + ip.f * ((double)urow[ip.r1] * sig);
+            if (s->swap)
+                S[(long long)qq * M + r] = T(y);
+            else
+                S[o] = T(y);
+        }
     }
     __syncthreads();
     __threadfence_block();
@@ -348,7 +579,6 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     // entry always is).  Rows are scanned by one wave each; columns in strips
     // of 64 (one lane per column, rows in order) so that every load of S is
     // a contiguous row segment.  Bests are recomputed only when stale (-2).
-    const int nR = nB, nC = nA;
     int* rstate = reinterpret_cast<int*>(smem);
     int* rbest = rstate + nR;
     int* cstate = rbest + nR;
@@ -432,13 +662,13 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
 
     const int64_t mo = J.match_off ? J.match_off[p] : 0;
     double sc = 0.0;
-    for (int i = tid; i < nB; i += kFinishThreads) {
+    for (int i = tid; i < nR; i += kFinishThreads) {
         const int jj = rstate[i];
         if (jj >= 0) sc += (double)S[(long long)i * nC + jj];
         if (J.match) J.match[mo + i] = jj;
     }
     if (J.S_out) {
-        T* So = reinterpret_cast<T*>(J.S_out) + J.S_off[p];
+        T* So = reinterpret_cast<T*>(J.S_out) + (J.S_off ? J.S_off[p] : 0);
         for (long long o = tid; o < total; o += kFinishThreads) So[o] = S[o];
     }
     const double score = dev::block_sum<NW>(sc, red);
@@ -466,25 +696,32 @@ int set_large_attributes() {
     return e;
 }
 
-int launch_large(int dtype, const LargeJob& J, int grid, hipStream_t stream) {
+template <typename T>
+static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
     hipLaunchKernelGGL(large_init, dim3(J.n_pairs), dim3(256), 0, stream, J);
     int e = (int)hipGetLastError();
     if (e != 0) return e;
     hipLaunchKernelGGL(large_scan, dim3(1), dim3(1024), 0, stream, J);
     if ((e = (int)hipGetLastError()) != 0) return e;
-    for (int k = 1; k <= J.max_iter + 1; ++k) {
-        if (dtype == CFSIM_F64)
-            hipLaunchKernelGGL(large_step<double>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
-        else
-            hipLaunchKernelGGL(large_step<float>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
+    if (J.resize) {
+        hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, 0);
         if ((e = (int)hipGetLastError()) != 0) return e;
     }
+    for (int k = 1; k <= J.max_iter + 1; ++k) {
+        hipLaunchKernelGGL(large_step<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
+        if ((e = (int)hipGetLastError()) != 0) return e;
+        if (J.resize) {
+            hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
+            if ((e = (int)hipGetLastError()) != 0) return e;
+        }
+    }
     const size_t lds = large_finish_lds(J.max_nodes);
-    if (dtype == CFSIM_F64)
-        hipLaunchKernelGGL(large_finish<double>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
-    else
-        hipLaunchKernelGGL(large_finish<float>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
+    hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
     return (int)hipGetLastError();
+}
+
+int launch_large(int dtype, const LargeJob& J, int grid, hipStream_t stream) {
+    return dtype == CFSIM_F64 ? launch_large_t<double>(J, grid, stream) : launch_large_t<float>(J, grid, stream);
 }
 
 }  // namespace cfsim

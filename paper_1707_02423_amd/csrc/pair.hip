@@ -35,11 +35,42 @@ namespace {
 
 using namespace dev;
 
+// Even step: S_k = S * inv in place, d2 = ||S_k - S_{k-2}||^2 (FP64, each
+// thread in index order), S_{k-2} := S_k.  Loads are taken in batches of
+// eight before any store, so the S_{k-2} reads (global memory when it does not
+// fit LDS) overlap instead of waiting one by one.
+template <typename T, int NT>
+__device__ inline double normalise_step(T* S, T* Sp, long long total, T inv) {
+    constexpr int B = 8;
+    double d2 = 0.0;
+    for (long long t0 = threadIdx.x; t0 < total; t0 += B * NT) {
+        T a[B], b[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const long long t = t0 + u * NT;
+            a[u] = t < total ? S[t] : T(0);
+            b[u] = t < total ? Sp[t] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const long long t = t0 + u * NT;
+            if (t < total) {
+                const T sv = a[u] * inv;
+                const double d = (double)sv - (double)b[u];
+                S[t] = sv;
+                Sp[t] = sv;
+                d2 += d * d;
+            }
+        }
+    }
+    return d2;
+}
+
 // Steps a4-a6 with S in LDS (NCH = exact chunk count); S_{k-2} lives in a
 // third LDS buffer Sp_lds when the variant's budget holds it, else in the
 // workgroup's global slot Sp.  Returns the buffer holding the final S.
 template <typename T, int NT, int NCH>
-__device__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
+__device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
                                const Lists<T>& G, bool degenerate, T* Sp, T* Sp_lds, double* red) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
@@ -104,28 +135,9 @@ __device__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const Pair
         }
         // even k: normalise in place and take the step against S_{k-2}
         // (every entry is final after the barrier above: flat, unrolled loops)
-        double d2 = 0.0;
         T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
-        const int total = nR * nC;
-        if (Sp_lds) {
-#pragma unroll 4
-            for (int t = threadIdx.x; t < total; t += NT) {
-                const T sv = Sw[t] * inv;
-                const double d = (double)sv - (double)Sp_lds[t];
-                Sw[t] = sv;
-                Sp_lds[t] = sv;
-                d2 += d * d;
-            }
-        } else {
-#pragma unroll 4
-            for (int t = threadIdx.x; t < total; t += NT) {
-                const T sv = Sw[t] * inv;
-                const double d = (double)sv - (double)Sp[t];
-                Sw[t] = sv;
-                Sp[t] = sv;
-                d2 += d * d;
-            }
-        }
+        const double d2 = Sp_lds ? normalise_step<T, NT>(Sw, Sp_lds, nR * nC, inv)
+                                 : normalise_step<T, NT>(Sw, Sp, nR * nC, inv);
         sigma = T(1);
         out.delta = sqrt(block_sum<NW>(d2, red + 2 * NW));
         if (out.delta < J.tol) {
@@ -146,7 +158,7 @@ __device__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const Pair
 // workgroup, L2/MALL resident while the pair runs).  Chunks are processed one
 // after the other, each with its lane lists reloaded from LDS.
 template <typename T, int NT>
-__device__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const Lists<T>& G, T* S0, T* S1, T* Sp,
+__device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const Lists<T>& G, T* S0, T* S1, T* Sp,
                                   bool degenerate, double* red) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
@@ -204,15 +216,8 @@ __device__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const L
             sigma = inv;
             continue;
         }
-        double d2 = 0.0;
         T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
-        for (long long t = threadIdx.x; t < total; t += NT) {
-            const T sv = Sw[t] * inv;
-            Sw[t] = sv;
-            const double d = (double)sv - (double)Sp[t];
-            d2 += d * d;
-            Sp[t] = sv;
-        }
+        const double d2 = normalise_step<T, NT>(Sw, Sp, total, inv);
         sigma = T(1);
         out.delta = sqrt(block_sum<NW>(d2, red + 2 * NW));
         if (out.delta < J.tol) {
@@ -233,7 +238,7 @@ __device__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const L
 // Step a7 and the outputs: greedy matching by locally-dominant rounds on the
 // stored S (compute orientation), score in original row order, S_out, result.
 template <typename T, int NT>
-__device__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
+__device__ __forceinline__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
                                 const T* S, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
                                 double* red, int* s_count) {
     constexpr int NW = NT / kWave;
@@ -366,7 +371,7 @@ __device__ void match_and_write(const PairJob& J, int p, const GraphRef& A, cons
 }
 
 template <typename T, int NT, int NCHMAX>
-__device__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+__device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
     GraphRef A{}, B{};
     cfsim_pair_result* res;
     PairShape sh{};
@@ -404,7 +409,7 @@ __device__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* r
 }
 
 template <typename T, int NT>
-__device__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+__device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
     GraphRef A{}, B{};
     cfsim_pair_result* res;
     PairShape sh{};
@@ -431,7 +436,7 @@ __device__ void global_pair(const PairJob& J, int p, unsigned char* smem, double
 // Persistent driver: one pair at a time per workgroup, pulled from the
 // bucket's queue (or the single pair of the plain path).
 template <bool GLOBAL, typename T, int NT, int NCH>
-__device__ inline void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count) {
+__device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count) {
     if (J.single) {
         if (blockIdx.x == 0) {
             if constexpr (GLOBAL)

@@ -35,30 +35,92 @@ __device__ inline double uni(double x) {
 __device__ inline float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ inline double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
+// Wave reductions without LDS round trips: DPP moves inside each 16-lane row
+// (partner = lane ^ 1, lane ^ 2, then the mirrored lane of the half row and of
+// the row, which after the first two steps combine disjoint groups), then the
+// four row results are read with readlane and combined in a fixed order.
+// Every lane returns the same value; the whole wave must be active.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
+template <int CTRL>
+__device__ inline int dpp(int x) {
+    return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ inline float dpp(float x) {
+    return __int_as_float(dpp<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ inline double dpp(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp<CTRL>((int)(b & 0xffffffffll)), hi = dpp<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline int lane_value(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ inline float lane_value(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ inline double lane_value(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double wave_sum(double x) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
-    return x;
+    x += dpp<kDppXor1>(x);
+    x += dpp<kDppXor2>(x);
+    x += dpp<kDppHalfMirror>(x);
+    x += dpp<kDppMirror>(x);
+    return (lane_value(x, 0) + lane_value(x, 16)) + (lane_value(x, 32) + lane_value(x, 48));
 }
 __device__ inline int wave_max(int x) {
-    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, kWave));
-    return x;
+    x = max(x, dpp<kDppXor1>(x));
+    x = max(x, dpp<kDppXor2>(x));
+    x = max(x, dpp<kDppHalfMirror>(x));
+    x = max(x, dpp<kDppMirror>(x));
+    return max(max(lane_value(x, 0), lane_value(x, 16)), max(lane_value(x, 32), lane_value(x, 48)));
 }
 template <typename T>
 __device__ inline bool better(T v, int k, T bv, int bk) {
     return v > bv || (v == bv && k < bk);
 }
+template <int CTRL, typename T>
+__device__ inline void argmax_step(T& v, int& k, int& c) {
+    const T ov = dpp<CTRL>(v);
+    const int ok = dpp<CTRL>(k);
+    const int oc = dpp<CTRL>(c);
+    if (better(ov, ok, v, k)) {
+        v = ov;
+        k = ok;
+        c = oc;
+    }
+}
+// Best (value desc, key asc) over the wave; (v, k, c) of the winner in every lane.
 template <typename T>
 __device__ inline void wave_argmax(T& v, int& k, int& c) {
-    for (int o = 32; o > 0; o >>= 1) {
-        const T ov = __shfl_xor(v, o, kWave);
-        const int ok = __shfl_xor(k, o, kWave);
-        const int oc = __shfl_xor(c, o, kWave);
-        if (better(ov, ok, v, k)) {
-            v = ov;
-            k = ok;
-            c = oc;
+    argmax_step<kDppXor1>(v, k, c);
+    argmax_step<kDppXor2>(v, k, c);
+    argmax_step<kDppHalfMirror>(v, k, c);
+    argmax_step<kDppMirror>(v, k, c);
+    T bv = lane_value(v, 0);
+    int bk = lane_value(k, 0), bc = lane_value(c, 0);
+#pragma unroll
+    for (int r = 16; r < 64; r += 16) {
+        const T rv = lane_value(v, r);
+        const int rk = lane_value(k, r), rc = lane_value(c, r);
+        if (better(rv, rk, bv, bk)) {
+            bv = rv;
+            bk = rk;
+            bc = rc;
         }
     }
+    v = bv;
+    k = bk;
+    c = bc;
 }
 
 // Neighbour lists of the lane's column in one 64-column chunk, padded with

@@ -203,7 +203,6 @@ def test_bucket_kernel_names():
 
 @pytest.mark.parametrize("kw,n_pairs,ws,opt_kw,code,text", [
     ({}, -1, 1 << 40, {}, -1, "n_pairs"),
-    ({}, 70000, 1 << 40, {}, -6, "65535"),
     (dict(max_nodes=9000), 5, 1 << 40, {}, -6, "8192"),
     ({}, 5, 1 << 40, dict(max_iter=5000), -6, "4096"),
     ({}, 5, 16, {}, -5, "workspace"),
@@ -227,3 +226,29 @@ def test_large_workspace_size():
     assert one >= 4 * 2048 * 2048 * 4
     assert L.cfsim_large_workspace_size(None, ctypes.byref(s), 64, ctypes.byref(opt)) >= 64 * 4 * 2048 * 2048 * 4
     assert L.cfsim_large_workspace_size(None, ctypes.byref(_set(max_nodes=9000)), 1, ctypes.byref(opt)) == 0
+
+
+def test_resize_limits_and_unsupported_calls():
+    L = cf.lib()
+    opt = cf.options("f32", resize="bilinear")
+    s = _set(max_nodes=9000)
+    assert L.cfsim_score_batch(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None, None,
+                               None, None, 0x1000, 1 << 40, None) == -6
+    assert "8192" in L.cfsim_last_error().decode()
+    assert L.cfsim_batch_workspace_size(None, ctypes.byref(s), 5, ctypes.byref(opt)) == 0
+    s = _set()
+    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None) == -6
+    assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
+                                  0x1000, 0x1000, 0x1000, None, 8, 0x1000, 1 << 40, None) == -6
+    opt_long = cf.options("f32", max_iter=5000, resize="bilinear")
+    A, B = _graph(), _graph(4, 3)
+    assert _call_score(A, B, opt_long) == -6
+
+
+def test_resize_workspace_sizes():
+    L = cf.lib()
+    opt = cf.options("f32", resize="bilinear")
+    # plain: one pair, six n_M^2 slots
+    assert L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >= 6 * 16 * 16 * 4
+    s = _set(max_nodes=128)
+    assert L.cfsim_batch_workspace_size(None, ctypes.byref(s), 100, ctypes.byref(opt)) >= 100 * 6 * 128 * 128 * 4

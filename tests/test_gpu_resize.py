@@ -1,0 +1,122 @@
+"""Parity of the scale-to-common-size mode (bilinear resize, Section 3.1)
+with the FP64 oracle, through cfsim_score and cfsim_score_batch."""
+import numpy as np
+import pytest
+
+import oracle
+from cfgsynth import CFG, Grammar, config_graphs, make_cfg
+from tests.parity import check_matching, oracle_pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1707_02423_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(cf):
+    return cf.Context(0)
+
+
+def _graphs(sizes, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for n in sizes:
+        if n == 1:
+            out.append(CFG(1, np.array([0], np.int32), np.array([0], np.int32), np.array([3.0])))
+        else:
+            out.append(make_cfg(n, Grammar(counts="trip"), rng))
+    return out
+
+
+def _check(S, match, res, ref, dtype):
+    gate = 1e-10 if dtype == "f64" else 1e-5
+    assert S.shape == ref.S.shape
+    assert rel_err(S, ref.S) <= gate
+    if dtype == "f64":
+        assert res["iters"] == ref.iters and res["status"] == ref.status
+        assert abs(res["nu"] - ref.nu) <= 1e-10 * max(ref.nu, 1.0)
+    check_matching(S, match, ref.S)
+    S64 = S.astype(np.float64)
+    assert abs(res["score"] - sum(S64[i, j] for i, j in enumerate(match) if j >= 0)) < 1e-12
+
+
+@pytest.mark.parametrize("nA,nB", [(9, 30), (30, 9), (12, 16), (16, 16), (1, 5), (5, 1), (70, 45), (3, 128),
+                                   (127, 128)])
+def test_resize_plain_fp64(cf, ctx, nA, nB):
+    graphs = _graphs([nA, nB], seed=nA * 131 + nB)
+    gs = cf.pack(ctx, graphs)
+    r = cf.score(ctx, gs, 0, 1, dtype="f64", resize="bilinear")
+    ref = oracle_pair(graphs, 0, 1, resize="bilinear")
+    _check(r["S"], r["match"], r, ref, "f64")
+
+
+def test_resize_workload0_pair(cf, ctx):
+    w = config_graphs(0)
+    gs = cf.pack(ctx, w["graphs"])
+    r = cf.score(ctx, gs, 0, 1, dtype="f64", resize="bilinear")
+    ref = oracle_pair(w["graphs"], 0, 1, resize="bilinear")
+    assert r["S"].shape == (16, 16)
+    _check(r["S"], r["match"], r, ref, "f64")
+
+
+@pytest.mark.parametrize("max_iter,tol", [(1, 1e-12), (2, 1e-12), (3, 0.0), (8, 0.0), (200, 1e-4)])
+def test_resize_iteration_controls(cf, ctx, max_iter, tol):
+    graphs = _graphs([20, 37], seed=17)
+    gs = cf.pack(ctx, graphs)
+    r = cf.score(ctx, gs, 1, 0, dtype="f64", max_iter=max_iter, tol=tol, resize="bilinear")
+    ref = oracle_pair(graphs, 1, 0, max_iter, tol, resize="bilinear")
+    _check(r["S"], r["match"], r, ref, "f64")
+
+
+def test_resize_degenerate_pair(cf, ctx):
+    graphs = _graphs([12], seed=2)
+    graphs.append(CFG(5, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([0.0, 0.0])))
+    gs = cf.pack(ctx, graphs)
+    r = cf.score(ctx, gs, 1, 0, dtype="f64", resize="bilinear")
+    ref = oracle_pair(graphs, 1, 0, resize="bilinear")
+    assert ref.status == oracle.DEGENERATE and r["status"] == cf.DEGENERATE
+    _check(r["S"], r["match"], r, ref, "f64")
+
+
+def test_resize_batch_fp32_workload1_subset(cf, ctx):
+    w = config_graphs(1, scale=10 / 256)
+    g = w["graphs"]
+    gs = cf.pack(ctx, g)
+    res, matches, Ss = cf.score_batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", resize="bilinear",
+                                      want_S=True)
+    assert len(res) == 45
+    for p in range(len(res)):
+        ref = oracle_pair(g, int(w["pair_a"][p]), int(w["pair_b"][p]), resize="bilinear")
+        assert Ss[p].shape == ref.S.shape
+        assert rel_err(Ss[p], ref.S) <= 1e-5, p
+        check_matching(Ss[p], matches[p], ref.S)
+
+
+def test_resize_batch_fp64_agrees_with_plain_and_replays(cf, ctx):
+    graphs = _graphs([6, 20, 33, 64, 90], seed=8)
+    pa, pb = np.triu_indices(len(graphs), k=0)
+    pa, pb = pa.astype(np.int32), pb.astype(np.int32)
+    gs = cf.pack(ctx, graphs)
+    b = cf.Batch(ctx, gs, pa, pb, dtype="f64", resize="bilinear", want_S=True)
+    b.run()
+    torch.cuda.synchronize()
+    r1, S1 = b.results().tobytes(), b.S.clone()
+    Ss, ms, res = b.S_list(), b.matches(), b.results()
+    for p in range(len(pa)):
+        ref = oracle_pair(graphs, int(pa[p]), int(pb[p]), resize="bilinear")
+        assert res["iters"][p] == ref.iters and res["status"][p] == ref.status
+        assert rel_err(Ss[p], ref.S) <= 1e-10
+        check_matching(Ss[p], ms[p], ref.S)
+    for _ in range(2):
+        b.res.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        assert b.results().tobytes() == r1 and torch.equal(b.S, S1)
