@@ -135,6 +135,89 @@ def plain_leg(ctx, gs, pa, pb, res, n_sub, stream):
                 plain_vs_batched_max_score_diff=float(np.max(np.abs(plain_res["score"] - res["score"][sub]))))
 
 
+def _time_ms(fn, reps, stream):
+    """Average milliseconds of fn() over reps calls (HIP events on `stream`)."""
+    import torch
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def workload_legs(ctx, stream, reps=3):
+    """The other hot-path rows, each on its own synthetic workload: large pairs
+    (tiled path), query-vs-database with top-16, the reverse mode, and the
+    scale-to-common-size mode of the all-pairs batch.  Inputs resident in HBM;
+    every figure is the average of `reps` timed calls after one warm-up."""
+    import torch
+    import paper_1707_02423_amd as cf
+    from cfgsynth import config_graphs
+    out = {}
+
+    # a9: 64 pairs, 512-2048 nodes, one tiled launch sequence (HIP graph)
+    w = config_graphs(2)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, path="large")
+    b.run()
+    torch.cuda.synchronize()
+    ms = _time_ms(b.run, reps, stream)
+    r = b.results()
+    nA, nB = b.nA.astype(np.float64), b.nB.astype(np.float64)
+    it = r["iters"].astype(np.float64)
+    # per update: read the previous iterate and write the new one (8 B per entry),
+    # plus the two iterates of the even-step change every other update
+    alg_bytes = float(np.sum(it * nA * nB * (8.0 + 4.0)))
+    out["large_pairs"] = dict(workload="64 pairs of synthetic CFGs, n ~ U[512,2048], FP32, <=200 updates",
+                              ms_per_call=ms, pairs_per_s=len(r) / (ms * 1e-3),
+                              hbm_roofline=dict(bound="hbm", achieved=alg_bytes / (ms * 1e-3) / 1e9, peak=8000.0,
+                                                unit="GB/s", frac=alg_bytes / (ms * 1e-3) / 8e12),
+                              status_counts={int(k): int(v) for k, v in zip(*np.unique(r["status"], return_counts=True))})
+    del b, gs
+
+    # a8 + a11: a 200-node query against 65,536 power-law graphs, then top-16
+    w = config_graphs(4)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=False)
+    b.run()
+    b.topk(16)
+    torch.cuda.synchronize()
+    ms = _time_ms(b.run, reps, stream)
+    ms_topk = _time_ms(lambda: b.topk(16), reps, stream)
+    out["query_db"] = dict(workload="200-node query vs 65,536 CFGs (p(n) ~ n^-2 on [4,512]), FP32, top-16",
+                           ms_per_call=ms, pairs_per_s=len(w["pair_a"]) / (ms * 1e-3), topk_ms=ms_topk)
+    del b, gs
+
+    # a10: 1,024 pairs n ~ U[16,256], forward then reverse mode (checkpoints every 8)
+    w = config_graphs(3)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True)
+    b.run()
+    gsc = torch.ones(len(w["pair_a"]), dtype=torch.float64, device=gs.w.device)
+    gw = torch.zeros_like(gs.w)
+    cf.backward(b, gsc, gw, checkpoint_every=8)
+    torch.cuda.synchronize()
+    ms_f = _time_ms(b.run, reps, stream)
+    ms_b = _time_ms(lambda: cf.backward(b, gsc, gw, checkpoint_every=8), reps, stream)
+    out["backward"] = dict(workload="1,024 pairs n ~ U[16,256], FP32, gradient w.r.t. every edge weight",
+                           forward_ms=ms_f, backward_ms=ms_b, pairs_per_s_fwd_bwd=len(w["pair_a"]) / ((ms_f + ms_b) * 1e-3))
+    del b, gs
+
+    # a2: the all-pairs batch with the bilinear scale to a common size
+    w = config_graphs(1)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", resize="bilinear", want_match=True)
+    b.run()
+    torch.cuda.synchronize()
+    ms = _time_ms(b.run, max(1, reps - 1), stream)
+    out["resize"] = dict(workload="all 32,640 pairs of the 256-CFG batch, bilinear scale to a common size, FP32",
+                         ms_per_call=ms, pairs_per_s=len(w["pair_a"]) / (ms * 1e-3))
+    del b, gs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +228,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=3, help="timed eager passes for per-kernel durations")
+    ap.add_argument("--no-legs", action="store_true", help="skip the other workloads (large pairs, query, ...)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (profiler byte-counter calibration)")
     args = ap.parse_args()
@@ -296,6 +380,8 @@ def main():
     }
     line.update(plain)
     line.update(ver)
+    if not args.no_legs:
+        line["workloads"] = workload_legs(ctx, stream)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(n_pairs, args.cpu_sample)
     print(json.dumps(line))

@@ -197,9 +197,9 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
  * cfsim_score_batch, for pairs whose lists do not fit the batched kernels
  * (those report CFSIM_INVALID_INPUT there).  The iterates live in the
  * workspace (HBM); every update is one launch over the tiles of all pairs of
- * the call, and the whole sequence (max_iter + 4 launches, twice as many
- * updates launches with resize) is captured once into a HIP graph cached in
- * the context.  This tiled path also serves every resized pair (opt->resize =
+ * the call, followed by a per-pair reduction launch; the whole sequence
+ * (about 2 * max_iter launches, 3 * max_iter with resize) is captured once
+ * into a HIP graph cached in the context.  This tiled path also serves every resized pair (opt->resize =
  * CFSIM_RESIZE_BILINEAR) of cfsim_score and cfsim_score_batch.  Limits:
  * graphs of at most 8192 nodes (set->max_nodes), max_iter at most 4096;
  * otherwise CFSIM_E_UNSUPPORTED.  ws is a device workspace of

@@ -43,12 +43,13 @@ __device__ double apply_M(const T* src, T* dst, T scale, const PairShape& sh, co
     for (int ch = 0; ch < sh.nchunk; ++ch) {
         LaneList<T> L[1];
         int col[1];
-        bool cv[1], ovf[1];
+        bool cv[1];
+        uint64_t ovf[1];
         lane_setup(G, ch, nC, L[0], col[0], cv[0], ovf[0]);
         for (int i = wave; i < nR; i += NW) {
             const RowRec<T> rr = G.rec[i];
             T y[1];
-            update_row<T, 1>(Sb, rowb, i, rr, G, L, ovf, ovf[0], col, cv, y);
+            update_row<T, 1>(Sb, rowb, i, rr, G, L, ovf, ovf[0] != 0, col, cv, y, ch);
             const T v = y[0] * scale;
             if (cv[0]) {
                 dst[(long long)i * nC + col[0]] = v;

@@ -177,14 +177,16 @@ void append_key(std::vector<unsigned char>& k, const X& x) {
 }
 
 // Large-pair (tiled) workspace: state[n_pairs] | tile_off[n_pairs + 1]
-//   | done[n_pairs] | part_nu, part_delta [n_pairs * large_tiles(max_nodes)]
+//   | part_nu, part_delta, tile_pair [n_pairs * large_tiles(max_nodes)]
+//   | node records [n_pairs][2][max_nodes]
 //   | nslots iterate slots of max_nodes^2 per pair (4, or 6 when resized)
 int large_nslots(const cfsim_options* o) { return o->resize == CFSIM_RESIZE_BILINEAR ? 6 : 4; }
 
 size_t large_ws_bytes(int64_t n_pairs, int max_nodes, int esize, int nslots) {
     const size_t tiles = (size_t)n_pairs * (size_t)cfsim::large_tiles(max_nodes);
     return align256((size_t)n_pairs * sizeof(cfsim::LargeState)) + align256((size_t)(n_pairs + 1) * 8) +
-           align256((size_t)n_pairs * 4) + 2 * align256(tiles * 8) +
+           2 * align256(tiles * 8) + align256(tiles * 4) +
+           align256((size_t)n_pairs * 2 * max_nodes * cfsim::large_rec_bytes(esize)) +
            (size_t)n_pairs * nslots * (size_t)global_slot_elems(max_nodes) * (size_t)esize;
 }
 
@@ -208,12 +210,14 @@ cfsim::LargeJob large_job(const cfsim_options* opt, int64_t n_pairs, int max_nod
     p += align256((size_t)n_pairs * sizeof(cfsim::LargeState));
     J.tile_off = reinterpret_cast<long long*>(p);
     p += align256((size_t)(n_pairs + 1) * 8);
-    J.done = reinterpret_cast<int*>(p);
-    p += align256((size_t)n_pairs * 4);
     J.part_nu = reinterpret_cast<double*>(p);
     p += align256(tiles * 8);
     J.part_delta = reinterpret_cast<double*>(p);
     p += align256(tiles * 8);
+    J.tile_pair = reinterpret_cast<int*>(p);
+    p += align256(tiles * 4);
+    J.recs = p;
+    p += align256((size_t)n_pairs * 2 * max_nodes * cfsim::large_rec_bytes(esize_of(opt->dtype)));
     J.bufs = p;
     J.nslots = large_nslots(opt);
     J.slot_elems = global_slot_elems(max_nodes);

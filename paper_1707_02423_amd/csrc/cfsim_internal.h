@@ -276,15 +276,18 @@ struct LargeJob {
     // workspace
     LargeState* st;      // [n_pairs]
     long long* tile_off; // [n_pairs + 1]
-    int* done;           // [n_pairs] tiles finished in the current launch
+    int* tile_pair;      // [tiles] pair of each tile
     double* part_nu;     // [tiles] squared-norm partials of Y
     double* part_delta;  // [tiles] squared partials of S_{k-1} - S_{k-3}
     void* bufs;          // [n_pairs][nslots][slot_elems]: 4 rotating iterates (+ V, S when resized)
     int nslots;
     long long slot_elems;
+    void* recs;          // [n_pairs][2][max_nodes] node records: rows of the row graph, columns of the column graph
 };
 
 constexpr int kLargeMaxNodes = 8192;  // bound of the finish kernel's LDS matching state
+// Bytes of one node record of the tiled path (first 2 successors, 3 predecessors).
+__host__ __device__ inline size_t large_rec_bytes(int esize) { return esize == 8 ? 80 : 48; }
 __host__ __device__ inline long long large_tiles(int n) { return (long long)((n + 31) / 32) * ((n + 63) / 64); }
 int large_step_grid(int num_cus);
 int set_large_attributes();

@@ -4,9 +4,12 @@
 // S no longer fits a workgroup's LDS, so every update is one grid-wide launch
 // over tiles of all pairs of the call, with the iterates in HBM (the MI355X
 // last-level cache holds a pair's working set).  The host captures the whole
-// sequence into one HIP graph.  The last workgroup to finish a pair's tiles in
-// a launch (counted with a device-scope atomic) reduces the pair's per-tile
-// FP64 partials in tile order, so every reduction is deterministic.
+// sequence into one HIP graph.  Every tile writes FP64 partials of the norms;
+// a small per-pair kernel after each update sums them in tile order (so every
+// reduction is deterministic) and takes the stopping decision.  A kernel
+// boundary is the cheap synchronisation here: on MI355X a device-scope fence
+// writes back and invalidates the XCD's whole L2, which a per-tile fence
+// would do thousands of times per update.
 //
 // Plain operator (no resize): four buffers rotate per pair; launch k reads
 // Y_{k-1} with sigma_{k-1} = 1/nu_{k-1} folded into the update and writes the
@@ -23,8 +26,8 @@
 //   U_k = M(V_{k-1}) / nu_{k-1},  V_k = U_k G,  nu_k^2 = <U_k, V_k> = ||Y_k||^2,
 //   delta_k^2 = <D, D G> with D = U_k / nu_k - U_{k-2} / nu_{k-2},
 // and S_k = U_k R^T / nu_k is expanded once at the end.  S_0 = 1/M is
-// U_0 = 1/M (every row of R sums to 1).  Each update is then two launches:
-// large_step (U) and large_gram (V, the norms and the stopping decision).
+// U_0 = 1/M (every row of R sums to 1).  Each update is then three launches:
+// large_step (U), large_gram (V and the norm partials), large_reduce.
 #include "cfsim_internal.h"
 #include "pair_device.h"
 
@@ -57,14 +60,44 @@ __device__ inline T* buf_of(const LargeJob& J, int p, int b) {
     return reinterpret_cast<T*>(J.bufs) + ((long long)p * J.nslots + b) * J.slot_elems;
 }
 
-__device__ inline int pair_of_tile(const LargeJob& J, long long t) {
-    int lo = 0, hi = J.n_pairs;  // largest p with tile_off[p] <= t
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (J.tile_off[mid] <= t) lo = mid; else hi = mid;
-    }
-    return lo;
+// First successors / predecessors of one node with their weights, the list
+// lengths (which may exceed the slots), zero-weight padding.
+template <typename T>
+struct alignas(16) NodeRec {
+    int ns, np;
+    int su[kLS];
+    int pu[kLP];
+    T sw[kLS];
+    T pw[kLP];
+};
+static_assert(sizeof(NodeRec<float>) == 48 && sizeof(NodeRec<double>) == 80, "large_rec_bytes()");
+
+// Pair p's records: rows of the row graph (which = 0), columns of the column graph (1).
+template <typename T>
+__device__ inline NodeRec<T>* recs_of(const LargeJob& J, int p, int which) {
+    return reinterpret_cast<NodeRec<T>*>(J.recs) + ((long long)p * 2 + which) * J.max_nodes;
 }
+
+template <typename T>
+__device__ inline NodeRec<T> make_rec(const GraphRef& G, int v) {
+    NodeRec<T> r;
+    const int sb = G.rp[v], pb = G.cp[v];
+    r.ns = G.rp[v + 1] - sb;
+    r.np = G.cp[v + 1] - pb;
+#pragma unroll
+    for (int q = 0; q < kLS; ++q) {
+        r.su[q] = q < r.ns ? G.ci[sb + q] : 0;
+        r.sw[q] = q < r.ns ? T(G.w[sb + q]) : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kLP; ++q) {
+        r.pu[q] = q < r.np ? G.ri[pb + q] : 0;
+        r.pw[q] = q < r.np ? T(G.w[G.eid[pb + q]]) : T(0);
+    }
+    return r;
+}
+
+__device__ inline int pair_of_tile(const LargeJob& J, long long t) { return J.tile_pair[t]; }
 
 __device__ inline bool pair_graphs(const LargeJob& J, int p, GraphRef* A, GraphRef* B) {
     if (J.single) {
@@ -145,7 +178,9 @@ __device__ inline void gram_entries(int u, int m, int M, double* d, double* e) {
 }
 
 // ---------------------------------------------------------------- set-up
-// One workgroup per pair: validity, degeneracy, state shape, initial state.
+// One workgroup per pair: validity, degeneracy, state shape, initial state,
+// and the node records of the row graph's rows and the column graph's columns.
+template <typename T>
 __global__ __launch_bounds__(256) void large_init(LargeJob J) {
     const int p = blockIdx.x;
     __shared__ int pos[2];
@@ -181,8 +216,15 @@ __global__ __launch_bounds__(256) void large_init(LargeJob J) {
         s->nu = 0.0;
         s->delta = __builtin_inf();
         for (int b = 0; b < 4; ++b) s->nu_k[b] = 1.0;
-        J.done[p] = 0;
     }
+    if (!ok) return;
+    const bool swap = rz && nB < nA;
+    const GraphRef& Rg = swap ? A : B;
+    const GraphRef& Cg = swap ? B : A;
+    NodeRec<T>* rr = recs_of<T>(J, p, 0);
+    NodeRec<T>* cr = recs_of<T>(J, p, 1);
+    for (int v = threadIdx.x; v < Rg.n; v += 256) rr[v] = make_rec<T>(Rg, v);
+    for (int v = threadIdx.x; v < Cg.n; v += 256) cr[v] = make_rec<T>(Cg, v);
 }
 
 // Exclusive scan of the pairs' tile counts (one workgroup).
@@ -209,6 +251,14 @@ __global__ __launch_bounds__(1024) void large_scan(LargeJob J) {
     for (int p = lo; p < hi; ++p) {
         J.tile_off[p] = run;
         run += J.st[p].ntiles;
+    }
+}
+
+// Pair of every tile (so a tile finds its pair with one load).
+__global__ __launch_bounds__(256) void large_tile_map(LargeJob J) {
+    for (int p = blockIdx.x; p < J.n_pairs; p += gridDim.x) {
+        const long long t0 = J.tile_off[p], t1 = J.tile_off[p + 1];
+        for (long long t = t0 + threadIdx.x; t < t1; t += 256) J.tile_pair[t] = p;
     }
 }
 
@@ -242,70 +292,8 @@ __device__ inline Tile tile_at(const LargeJob& J, long long t, const LargeState*
     return x;
 }
 
-// Reduce the per-tile partials of pair p (called by the workgroup that
-// finished the pair's last tile of this launch) and decide whether the pair
-// stops.  k: launch index; compute: a new iterate was formed; want_delta:
-// the partials of delta_{k-1} were accumulated.
-__device__ void reduce_and_decide(const LargeJob& J, int p, int k, bool compute, bool want_delta, double* red) {
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    LargeState* s = J.st + p;
-    __threadfence();
-    const long long t0 = J.tile_off[p], nt = s->ntiles;
-    double a = 0.0, b = 0.0;
-    for (long long q = tid; q < nt; q += kStepThreads) {
-        a += J.part_nu[t0 + q];
-        b += J.part_delta[t0 + q];
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    __syncthreads();
-    if (lane == 0) {
-        red[wave] = a;
-        red[kNWStep + wave] = b;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double nu2s = 0.0, d2s = 0.0;
-        for (int w = 0; w < kNWStep; ++w) {
-            nu2s += red[w];
-            d2s += red[kNWStep + w];
-        }
-        J.done[p] = 0;
-        bool stop = false;
-        if (want_delta) {
-            const double delta = sqrt(d2s);
-            s->delta = delta;
-            if (delta < J.tol) {   // converged at the even step k - 1
-                s->final_step = k - 1;
-                s->nu = s->nu_k[(k - 1) & 3];
-                s->status = CFSIM_CONVERGED;
-                stop = true;
-            }
-        }
-        if (!stop && compute) {
-            const double nu = sqrt(nu2s);
-            s->nu_k[k & 3] = nu;
-            if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
-                s->final_step = k;
-                s->nu = nu;
-                s->status = CFSIM_HIT_MAX_ITER;
-                stop = true;
-            }
-        }
-        if (!stop && !compute) {               // launch max_iter + 1
-            s->final_step = J.max_iter;
-            s->nu = s->nu_k[J.max_iter & 3];
-            s->status = CFSIM_HIT_MAX_ITER;
-            stop = true;
-        }
-        if (stop) s->active = 0;
-    }
-}
-
-// Per-tile partials (fixed order: waves, then lanes), then the pair's last
-// tile of this launch reduces them.
-__device__ void tile_partials(const LargeJob& J, long long t, int p, int k, bool compute, bool want_delta,
-                              double nu2, double d2, double* red, int* last_flag) {
+// Per-tile partials (fixed order: waves, then lanes).
+__device__ void tile_partials(const LargeJob& J, long long t, double nu2, double d2, double* red) {
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     nu2 = wave_sum(nu2);
     d2 = wave_sum(d2);
@@ -322,13 +310,95 @@ __device__ void tile_partials(const LargeJob& J, long long t, int p, int k, bool
         }
         J.part_nu[t] = a;
         J.part_delta[t] = b;
-        __threadfence();
-        const int prev = atomicAdd(J.done + p, 1);
-        *last_flag = prev == J.st[p].ntiles - 1;
     }
     __syncthreads();
-    if (*last_flag) reduce_and_decide(J, p, k, compute, want_delta, red);
+}
+
+// After update launch k: one workgroup per active pair sums its tiles'
+// partials in tile order and decides whether the pair stops.  compute: a new
+// iterate was formed (k <= max_iter); want_delta: the partials of
+// delta_{k-1} were accumulated (odd k >= 3).
+__global__ __launch_bounds__(kStepThreads) void large_reduce(LargeJob J, int k) {
+    __shared__ double red[2 * kNWStep];
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    LargeState* s = J.st + p;
+    if (!s->active) return;
+    const bool compute = k <= J.max_iter;
+    const bool want_delta = (k & 1) && k >= 3;
+    const long long t0 = J.tile_off[p], nt = s->ntiles;
+    double a = 0.0, b = 0.0;
+    for (long long q = tid; q < nt; q += kStepThreads) {
+        a += J.part_nu[t0 + q];
+        b += J.part_delta[t0 + q];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (lane == 0) {
+        red[wave] = a;
+        red[kNWStep + wave] = b;
+    }
     __syncthreads();
+    if (tid != 0) return;
+    double nu2s = 0.0, d2s = 0.0;
+    for (int w = 0; w < kNWStep; ++w) {
+        nu2s += red[w];
+        d2s += red[kNWStep + w];
+    }
+    bool stop = false;
+    if (want_delta) {
+        const double delta = sqrt(d2s);
+        s->delta = delta;
+        if (delta < J.tol) {   // converged at the even step k - 1
+            s->final_step = k - 1;
+            s->nu = s->nu_k[(k - 1) & 3];
+            s->status = CFSIM_CONVERGED;
+            stop = true;
+        }
+    }
+    if (!stop && compute) {
+        const double nu = sqrt(nu2s);
+        s->nu_k[k & 3] = nu;
+        if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
+            s->final_step = k;
+            s->nu = nu;
+            s->status = CFSIM_HIT_MAX_ITER;
+            stop = true;
+        }
+    }
+    if (!stop && !compute) {               // launch max_iter + 1
+        s->final_step = J.max_iter;
+        s->nu = s->nu_k[J.max_iter & 3];
+        s->status = CFSIM_HIT_MAX_ITER;
+        stop = true;
+    }
+    if (stop) s->active = 0;
+}
+
+// Sum over a row's NS successor and NP predecessor terms (wave-uniform rows u
+// of the source iterate) of the lane column's gathered terms; every gather of
+// the row is independent, so they are all in flight together.
+template <typename T, int NS, int NP>
+__device__ inline T row_terms(const T* src, int nC, const int (&ru)[kLS], const T (&rw)[kLS], const int (&qu)[kLP],
+                              const T (&qw)[kLP], const NodeRec<T>& c) {
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        const T* row = src + (long long)ru[a] * nC;
+        T in = c.sw[0] * row[c.su[0]];
+#pragma unroll
+        for (int q = 1; q < kLS; ++q) in = dev::fma_t(c.sw[q], row[c.su[q]], in);
+        acc = dev::fma_t(rw[a], in, acc);
+    }
+#pragma unroll
+    for (int b = 0; b < NP; ++b) {
+        const T* row = src + (long long)qu[b] * nC;
+        T in = c.pw[0] * row[c.pu[0]];
+#pragma unroll
+        for (int q = 1; q < kLP; ++q) in = dev::fma_t(c.pw[q], row[c.pu[q]], in);
+        acc = dev::fma_t(qw[b], in, acc);
+    }
+    return acc;
 }
 
 // ---------------------------------------------------------------- the operator
@@ -341,7 +411,6 @@ __device__ void tile_partials(const LargeJob& J, long long t, int p, int k, bool
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
     __shared__ double red[2 * kNWStep];
-    __shared__ int last_flag;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const bool compute = k <= J.max_iter;
     const bool want_delta = (k & 1) && k >= 3;
@@ -354,8 +423,6 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         if (rz && !compute) continue;
         const Tile tl = tile_at(J, t, s, p);
         const int nR = s->nR, nC = s->nC;
-        GraphRef Rg, Cg;
-        state_graphs(J, p, s, &Rg, &Cg);
         const int j = tl.c0 + lane;
         const bool colv = j < nC;
         const T* src = rz ? buf_of<T>(J, p, kSlotV) : buf_of<T>(J, p, (k - 1) & 3);
@@ -367,41 +434,70 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         const bool first = k == 1 && !rz;                 // S_0 is the constant
         const bool old_is_s0 = k == 3;
         // the lane column's neighbour lists in Cg (padding has zero weight)
-        int sv[kLS], pv[kLP];
-        T sw[kLS], pw[kLP];
-        int ns = 0, np = 0, sb = 0, pb = 0;
-        if (colv) {
-            sb = Cg.rp[j];
-            ns = Cg.rp[j + 1] - sb;
-            pb = Cg.cp[j];
-            np = Cg.cp[j + 1] - pb;
-        }
-#pragma unroll
-        for (int q = 0; q < kLS; ++q) {
-            sv[q] = q < ns ? Cg.ci[sb + q] : 0;
-            sw[q] = q < ns ? T(Cg.w[sb + q]) : T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < kLP; ++q) {
-            pv[q] = q < np ? Cg.ri[pb + q] : 0;
-            pw[q] = q < np ? T(Cg.w[Cg.eid[pb + q]]) : T(0);
-        }
+        const NodeRec<T>* rrec = recs_of<T>(J, p, 0);
+        NodeRec<T> cr{};
+        if (colv) cr = recs_of<T>(J, p, 1)[j];
+        const int ns = cr.ns, np = cr.np;
         const bool ovf = uni(dev::wave_max(max(ns - kLS, np - kLP))) > 0;
+        // CSR lists are read only by the first update and by long lists
+        GraphRef Rg{}, Cg{};
+        int sb = 0, pb = 0;
+        if (first || ovf) {
+            state_graphs(J, p, s, &Rg, &Cg);
+            sb = colv ? Cg.rp[j] : 0;
+            pb = colv ? Cg.cp[j] : 0;
+        }
         double nu2 = 0.0, d2 = 0.0;
+        const int i0 = tl.r0 + wave * kRowsPerWave;
+        NodeRec<T> nxt = rrec[min(i0, nR - 1)];
         for (int rr = 0; rr < kRowsPerWave; ++rr) {
-            const int i = tl.r0 + wave * kRowsPerWave + rr;
+            const int i = i0 + rr;
             if (i >= nR) break;
+            const NodeRec<T> rw = nxt;
+            nxt = rrec[min(i + 1, nR - 1)];  // prefetch the wave's next row
             if (compute) {
                 T acc = T(0);
-                if (first) {
+                const int nsR = uni(rw.ns), npR = uni(rw.np);
+                if (!first && !ovf && nsR <= kLS && npR <= kLP) {
+                    int ru[kLS], qu[kLP];
+                    T rwt[kLS], qwt[kLP];
+#pragma unroll
+                    for (int a = 0; a < kLS; ++a) {
+                        ru[a] = uni(rw.su[a]);
+                        rwt[a] = uni(rw.sw[a]);
+                    }
+#pragma unroll
+                    for (int b = 0; b < kLP; ++b) {
+                        qu[b] = uni(rw.pu[b]);
+                        qwt[b] = uni(rw.pw[b]);
+                    }
+                    switch (nsR * 4 + npR) {
+                        case 0: break;
+                        case 1: acc = row_terms<T, 0, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 2: acc = row_terms<T, 0, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 3: acc = row_terms<T, 0, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 4: acc = row_terms<T, 1, 0>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 5: acc = row_terms<T, 1, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 6: acc = row_terms<T, 1, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 7: acc = row_terms<T, 1, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 8: acc = row_terms<T, 2, 0>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 9: acc = row_terms<T, 2, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        case 10: acc = row_terms<T, 2, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
+                        default: acc = row_terms<T, 2, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
+                    }
+                    acc *= sig;
+                } else if (first) {
                     // S_0 constant: Y_1[i][j] = c0 (outw_Rg(i) outw_Cg(j) + inw_Rg(i) inw_Cg(j))
                     T ra = T(0), rb = T(0), qa = T(0), qb = T(0);
-                    for (int e = 0; e < ns; ++e) ra += T(Cg.w[sb + e]);
-                    for (int e = 0; e < np; ++e) qa += T(Cg.w[Cg.eid[pb + e]]);
+                    if (colv) {
+                        for (int e = 0; e < ns; ++e) ra += T(Cg.w[sb + e]);
+                        for (int e = 0; e < np; ++e) qa += T(Cg.w[Cg.eid[pb + e]]);
+                    }
                     for (int e = Rg.rp[i]; e < Rg.rp[i + 1]; ++e) rb += T(Rg.w[e]);
                     for (int e = Rg.cp[i]; e < Rg.cp[i + 1]; ++e) qb += T(Rg.w[Rg.eid[e]]);
                     acc = c0v * (rb * ra + qb * qa);
                 } else {
+                    if (!ovf) state_graphs(J, p, s, &Rg, &Cg);  // a row with long lists
                     const int e1 = uni(Rg.rp[i + 1]);
                     for (int e = uni(Rg.rp[i]); e < e1; ++e) {
                         const int u = uni(Rg.ci[e]);
@@ -409,7 +505,7 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
                         const T* row = src + (long long)u * nC;
                         T in = T(0);
 #pragma unroll
-                        for (int q = 0; q < kLS; ++q) in = dev::fma_t(sw[q], row[sv[q]], in);
+                        for (int q = 0; q < kLS; ++q) in = dev::fma_t(cr.sw[q], row[cr.su[q]], in);
                         if (ovf)
                             for (int q = kLS; q < ns; ++q) in = dev::fma_t(T(Cg.w[sb + q]), row[Cg.ci[sb + q]], in);
                         acc = dev::fma_t(wu, in, acc);
@@ -421,7 +517,7 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
                         const T* row = src + (long long)u * nC;
                         T in = T(0);
 #pragma unroll
-                        for (int q = 0; q < kLP; ++q) in = dev::fma_t(pw[q], row[pv[q]], in);
+                        for (int q = 0; q < kLP; ++q) in = dev::fma_t(cr.pw[q], row[cr.pu[q]], in);
                         if (ovf)
                             for (int q = kLP; q < np; ++q)
                                 in = dev::fma_t(T(Cg.w[Cg.eid[pb + q]]), row[Cg.ri[pb + q]], in);
@@ -443,7 +539,7 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
             }
         }
         if (rz) continue;   // norms of resized pairs come from large_gram
-        tile_partials(J, t, p, k, compute, want_delta, nu2, d2, red, &last_flag);
+        tile_partials(J, t, nu2, d2, red);
     }
 }
 
@@ -454,7 +550,6 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void large_gram(LargeJob J, int k) {
     __shared__ double red[2 * kNWStep];
-    __shared__ int last_flag;
     __shared__ double gd[66], ge[66];  // G diagonal and coupling for columns c0 - 1 .. c0 + 64
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const bool compute = k <= J.max_iter;
@@ -516,7 +611,7 @@ __global__ __launch_bounds__(kStepThreads) void large_gram(LargeJob J, int k) {
             }
         }
         if (k == 0) continue;
-        tile_partials(J, t, p, k, compute, want_delta, nu2, d2, red, &last_flag);
+        tile_partials(J, t, nu2, d2, red);
     }
 }
 
@@ -572,13 +667,19 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
         }
     }
     __syncthreads();
+    // S^T in a free slot, so that a column's candidates are a contiguous line too
+    T* St = rz ? buf_of<T>(J, p, kSlotU + ((f + 1) & 3)) : buf_of<T>(J, p, (f + 1) & 3);
+    for (long long o = tid; o < total; o += kFinishThreads) {
+        const int r = (int)(o / nC), c = (int)(o - (long long)r * nC);
+        St[(long long)c * nR + r] = S[o];
+    }
+    __syncthreads();
     __threadfence_block();
 
     // Greedy matching by locally dominant rounds: a free row and a free column
     // that are each other's best free partner are matched (the largest free
-    // entry always is).  Rows are scanned by one wave each; columns in strips
-    // of 64 (one lane per column, rows in order) so that every load of S is
-    // a contiguous row segment.  Bests are recomputed only when stale (-2).
+    // entry always is).  A stale best (-2) is recomputed by one wave scanning
+    // the row of S or the row of S^T: contiguous loads, eight per lane in flight.
     int* rstate = reinterpret_cast<int*>(smem);
     int* rbest = rstate + nR;
     int* cstate = rbest + nR;
@@ -594,48 +695,47 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     if (tid == 0) s_count = 0;
     __syncthreads();
     const int need = min(nR, nC);
-    const int nstrip = (nC + 63) / 64;
     int done = 0;
     while (done < need) {
-        for (int it = wave; it < nR + nstrip; it += NW) {
-            if (it < nR) {
-                const int r = it;
-                if (uni(rstate[r]) != -1 || uni(rbest[r]) != -2) continue;
-                T bv = T(-1);
-                int bk = INT_MAX, bc = -1;
-                const T* row = S + (long long)r * nC;
-                for (int c = lane; c < nC; c += kWave) {
-                    if (cstate[c] == -1) {
-                        const T v = row[c];
-                        const int key = r * nC + c;
-                        if (better(v, key, bv, bk)) {
-                            bv = v;
+        for (int it = wave; it < nR + nC; it += NW) {
+            const bool is_row = it < nR;
+            const int x = is_row ? it : it - nR;
+            if (is_row ? (uni(rstate[x]) != -1 || uni(rbest[x]) != -2)
+                       : (uni(cstate[x]) != -1 || uni(cbest[x]) != -2))
+                continue;
+            // candidates: row x of S (free columns) or row x of S^T (free rows)
+            const T* line = is_row ? S + (long long)x * nC : St + (long long)x * nR;
+            const int n = is_row ? nC : nR;
+            const int* other = is_row ? cstate : rstate;
+            const int kb = is_row ? x * nC : x, ks = is_row ? 1 : nC;
+            T bv = T(-1);
+            int bk = INT_MAX, bi = -1;
+            for (int y0 = lane; y0 < n; y0 += 8 * kWave) {
+                T v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int y = y0 + u * kWave;
+                    v[u] = y < n ? line[y] : T(-1);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int y = y0 + u * kWave;
+                    if (y < n && other[y] == -1) {
+                        const int key = kb + y * ks;
+                        if (better(v[u], key, bv, bk)) {
+                            bv = v[u];
                             bk = key;
-                            bc = c;
+                            bi = y;
                         }
                     }
                 }
-                wave_argmax(bv, bk, bc);
-                if (lane == 0) rbest[r] = bc;
-            } else {
-                const int c = (it - nR) * 64 + lane;
-                const bool mine = c < nC && cstate[c] == -1 && cbest[c] == -2;
-                if (__builtin_amdgcn_ballot_w64(mine) == 0) continue;
-                T bv = T(-1);
-                int bk = INT_MAX, br = -1;
-                for (int r = 0; r < nR; ++r) {
-                    if (uni(rstate[r]) != -1) continue;
-                    if (mine) {
-                        const T v = S[(long long)r * nC + c];
-                        const int key = r * nC + c;
-                        if (better(v, key, bv, bk)) {
-                            bv = v;
-                            bk = key;
-                            br = r;
-                        }
-                    }
-                }
-                if (mine) cbest[c] = br;
+            }
+            wave_argmax(bv, bk, bi);
+            if (lane == 0) {
+                if (is_row)
+                    rbest[x] = bi;
+                else
+                    cbest[x] = bi;
             }
         }
         __syncthreads();
@@ -698,10 +798,12 @@ int set_large_attributes() {
 
 template <typename T>
 static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
-    hipLaunchKernelGGL(large_init, dim3(J.n_pairs), dim3(256), 0, stream, J);
+    hipLaunchKernelGGL(large_init<T>, dim3(J.n_pairs), dim3(256), 0, stream, J);
     int e = (int)hipGetLastError();
     if (e != 0) return e;
     hipLaunchKernelGGL(large_scan, dim3(1), dim3(1024), 0, stream, J);
+    if ((e = (int)hipGetLastError()) != 0) return e;
+    hipLaunchKernelGGL(large_tile_map, dim3(J.n_pairs < 4096 ? J.n_pairs : 4096), dim3(256), 0, stream, J);
     if ((e = (int)hipGetLastError()) != 0) return e;
     if (J.resize) {
         hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, 0);
@@ -714,6 +816,8 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
             hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
         }
+        hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
+        if ((e = (int)hipGetLastError()) != 0) return e;
     }
     const size_t lds = large_finish_lds(J.max_nodes);
     hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);

@@ -80,12 +80,13 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
 
     LaneList<T> L[NCH];
     int col[NCH];
-    bool cv[NCH], ovf[NCH];
+    bool cv[NCH];
+    uint64_t ovf[NCH];
     bool any_ovf = false;
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
         lane_setup(G, ch, nC, L[ch], col[ch], cv[ch], ovf[ch]);
-        any_ovf |= ovf[ch];
+        any_ovf |= ovf[ch] != 0;
     }
 
     IterOut out{0.0, __builtin_inf(), 0, 0u, 0};
@@ -183,14 +184,15 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
         for (int ch = 0; ch < nchunk; ++ch) {
             LaneList<T> L[1];
             int col[1];
-            bool cv[1], ovf[1];
+            bool cv[1];
+            uint64_t ovf[1];
             lane_setup(G, ch, nC, L[0], col[0], cv[0], ovf[0]);
             RowRec<T> nxt = G.rec[min(wave, last)];
             for (int i = wave; i < nR; i += NW) {
                 const RowRec<T> rr = nxt;
                 nxt = G.rec[min(i + NW, last)];
                 T y[1];
-                update_row<T, 1>(Sb, rowb, i, rr, G, L, ovf, ovf[0], col, cv, y);
+                update_row<T, 1>(Sb, rowb, i, rr, G, L, ovf, ovf[0] != 0, col, cv, y, ch);
                 const T v = y[0] * sigma;
                 if (cv[0]) {
                     *reinterpret_cast<T*>(Nb + (long long)i * rowb + col[0] * esz) = v;

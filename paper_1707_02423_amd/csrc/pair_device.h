@@ -387,12 +387,53 @@ __device__ bool stage_pair(const GraphRef& R, const GraphRef& C, int nR, int nC,
     return !(anyR && anyC);
 }
 
+// Lane-list entries past kDS / kDP for the lanes in `mask` (one chunk), for a
+// row whose R terms sit in SGPRs.  Every access is wave-uniform (broadcast
+// LDS reads), so a column with a long list costs a few scalar-controlled
+// reads per row instead of a divergent loop in every lane.
+template <typename T>
+__device__ inline T row_extras(const unsigned char* Sb, uint64_t mask, int ch, const Lists<T>& G, int ns, int np,
+                               const int (&su)[kDS], const T (&sw)[kDS], const int (&pu)[kDP], const T (&pw)[kDP]) {
+    const int esz = (int)sizeof(T);
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    T add = T(0);
+    while (mask) {
+        const int l = (int)__builtin_ctzll(mask);
+        mask &= mask - 1;
+        const int4 ci = G.cinfo[ch * kWave + l];
+        const int se = uni(ci.y), pe = uni(ci.w);
+        T acc = T(0);
+        for (int q = uni(ci.x) + kDS; q < se; ++q) {
+            const Edge<T> e = G.csedge[q];
+            const int vo = uni(e.u) * esz;
+            T s = T(0);
+#pragma unroll
+            for (int a = 0; a < kDS; ++a)
+                if (a < ns) s = fma_t(sw[a], lds_at<T>(Sb, su[a] + vo), s);
+            acc = fma_t(uni(e.w), s, acc);
+        }
+        for (int q = uni(ci.z) + kDP; q < pe; ++q) {
+            const Edge<T> e = G.cpedge[q];
+            const int vo = uni(e.u) * esz;
+            T s = T(0);
+#pragma unroll
+            for (int b = 0; b < kDP; ++b)
+                if (b < np) s = fma_t(pw[b], lds_at<T>(Sb, pu[b] + vo), s);
+            acc = fma_t(uni(e.w), s, acc);
+        }
+        add += lane == l ? acc : T(0);
+    }
+    return add;
+}
+
 // One wave's update of row i: y[ch] for its NCH chunks (all S reads of the row
-// issued together), plus the overflow of long lane lists.
+// issued together), plus the entries of long lane lists.  L[ch] holds chunk
+// ch0 + ch; ovf[ch] is the (uniform) mask of its lanes whose lists exceed
+// kDS / kDP.
 template <typename T, int NCH>
 __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, const RowRec<T>& rr, const Lists<T>& G,
-                                  const LaneList<T> (&L)[NCH], const bool (&ovf)[NCH], bool any_ovf,
-                                  const int (&col)[NCH], const bool (&cv)[NCH], T (&y)[NCH]) {
+                                  const LaneList<T> (&L)[NCH], const uint64_t (&ovf)[NCH], bool any_ovf,
+                                  const int (&col)[NCH], const bool (&cv)[NCH], T (&y)[NCH], int ch0 = 0) {
     const int ns = uni(rr.ns), np = uni(rr.np);
     int su[kDS], pu[kDP];
     T sw[kDS], pw[kDP];
@@ -406,19 +447,23 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
         pu[q] = uni(rr.pu[q]);
         pw[q] = uni(rr.pw[q]);
     }
-    switch (ns <= 2 && np <= 2 ? ns * 3 + np : -1) {
+    const bool fixed = ns <= kDS && np <= kDP;
+    switch (fixed ? ns * 4 + np : -1) {
         case 0:
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
             break;
         case 1: row_fixed<T, NCH, 0, 1>(Sb, su, sw, pu, pw, L, y); break;
         case 2: row_fixed<T, NCH, 0, 2>(Sb, su, sw, pu, pw, L, y); break;
-        case 3: row_fixed<T, NCH, 1, 0>(Sb, su, sw, pu, pw, L, y); break;
-        case 4: row_fixed<T, NCH, 1, 1>(Sb, su, sw, pu, pw, L, y); break;
-        case 5: row_fixed<T, NCH, 1, 2>(Sb, su, sw, pu, pw, L, y); break;
-        case 6: row_fixed<T, NCH, 2, 0>(Sb, su, sw, pu, pw, L, y); break;
-        case 7: row_fixed<T, NCH, 2, 1>(Sb, su, sw, pu, pw, L, y); break;
-        case 8: row_fixed<T, NCH, 2, 2>(Sb, su, sw, pu, pw, L, y); break;
+        case 3: row_fixed<T, NCH, 0, 3>(Sb, su, sw, pu, pw, L, y); break;
+        case 4: row_fixed<T, NCH, 1, 0>(Sb, su, sw, pu, pw, L, y); break;
+        case 5: row_fixed<T, NCH, 1, 1>(Sb, su, sw, pu, pw, L, y); break;
+        case 6: row_fixed<T, NCH, 1, 2>(Sb, su, sw, pu, pw, L, y); break;
+        case 7: row_fixed<T, NCH, 1, 3>(Sb, su, sw, pu, pw, L, y); break;
+        case 8: row_fixed<T, NCH, 2, 0>(Sb, su, sw, pu, pw, L, y); break;
+        case 9: row_fixed<T, NCH, 2, 1>(Sb, su, sw, pu, pw, L, y); break;
+        case 10: row_fixed<T, NCH, 2, 2>(Sb, su, sw, pu, pw, L, y); break;
+        case 11: row_fixed<T, NCH, 2, 3>(Sb, su, sw, pu, pw, L, y); break;
         default: {
             const int2 st = G.rstart[i];
             row_loop<T, NCH>(Sb, rowb, G.sedge + uni(st.x), ns, G.pedge + uni(st.y), np, L, y);
@@ -426,24 +471,33 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
         }
     }
     if (any_ovf) {
-        const int2 st = G.rstart[i];
-        const Edge<T>* se = G.sedge + uni(st.x);
-        const Edge<T>* pe = G.pedge + uni(st.y);
+        if (fixed) {
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch)
-            if (ovf[ch]) y[ch] += row_overflow<T>(Sb, rowb, se, ns, pe, np, G.cinfo, G.csedge, G.cpedge, col[ch], cv[ch]);
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ovf[ch]) y[ch] += row_extras<T>(Sb, ovf[ch], ch0 + ch, G, ns, np, su, sw, pu, pw);
+        } else {
+            const int2 st = G.rstart[i];
+            const Edge<T>* se = G.sedge + uni(st.x);
+            const Edge<T>* pe = G.pedge + uni(st.y);
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ovf[ch])
+                    y[ch] += row_overflow<T>(Sb, rowb, se, ns, pe, np, G.cinfo, G.csedge, G.cpedge, col[ch], cv[ch]);
+        }
     }
 }
 
+// Lane lists of chunk ch; ovf = mask of the lanes whose lists are longer.
 template <typename T>
-__device__ inline void lane_setup(const Lists<T>& G, int ch, int nC, LaneList<T>& L, int& col, bool& cv, bool& ovf) {
+__device__ inline void lane_setup(const Lists<T>& G, int ch, int nC, LaneList<T>& L, int& col, bool& cv,
+                                  uint64_t& ovf) {
     const int c = ch * kWave + (int)(threadIdx.x & (kWave - 1));
     cv = c < nC;
     col = cv ? c : 0;
     load_lane(G.cinfo, G.csedge, G.cpedge, c, cv, L);
     const int4 ci = G.cinfo[col];
     const int extra = cv ? max(ci.y - ci.x - kDS, ci.w - ci.z - kDP) : 0;
-    ovf = uni(wave_max(extra)) > 0;
+    ovf = __builtin_amdgcn_ballot_w64(extra > 0);
 }
 
 // Reduces a per-wave double over the workgroup in a fixed order (every
