@@ -241,21 +241,30 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
 // stored S (compute orientation), score in original row order, S_out, result.
 template <typename T, int NT>
 __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
-                                const T* S, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
-                                double* red, int* s_count) {
+                                 const T* S, T* St, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
+                                 double* red, int* s_count) {
     constexpr int NW = NT / kWave;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wave = uni(tid / kWave);
     const int nR = sh.nR, nC = sh.nC;
+    const bool swp = sh.swap != 0;
     int* rstate = G.rstate;
     int* rbest = G.rbest;
     int* cstate = G.cstate;
     int* cbest = G.cbest;
     // Incremental rounds: a free row's best free column (and a free column's
     // best free row) only changes when that partner gets matched, so each round
-    // recomputes just the rows/columns marked stale (best = -2); mutual bests
-    // are matched.  All state lives in LDS; three barriers per round.
+    // recomputes just the stale rows/columns, listed in `todo` (items < nR are
+    // rows, the rest columns); mutual bests are matched.  Columns are scanned
+    // on S^T (St, the buffer the iteration no longer needs) so that every scan
+    // reads consecutive words.  The lists' LDS space (row records onwards) is
+    // free by now and holds `todo`.
+    int* todo = reinterpret_cast<int*>(G.rec);
+    for (long long o = tid; o < (long long)nR * nC; o += NT) {
+        const int r = (int)(o / nC), c = (int)(o - (long long)r * nC);
+        St[(long long)c * nR + r] = S[o];
+    }
     for (int r = tid; r < nR; r += NT) {
         rstate[r] = -1;
         rbest[r] = -2;
@@ -264,52 +273,56 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
         cstate[c] = -1;
         cbest[c] = -2;
     }
-    if (tid == 0) *s_count = 0;
+    for (int x = tid; x < nR + nC; x += NT) todo[x] = x;
+    if (tid == 0) {
+        s_count[0] = 0;
+        s_count[1] = nR + nC;
+    }
     __syncthreads();
     const int need = min(nR, nC);
-    const bool swp = sh.swap != 0;
     int done = 0;
     while (done < need) {
-        for (int it = wave; it < nR + nC; it += NW) {
-            if (it < nR) {
-                const int r = it;
-                if (uni(rstate[r]) != -1 || uni(rbest[r]) != -2) continue;
-                T bv = T(-1);
-                int bk = INT_MAX, bc = -1;
-                for (int c = lane; c < nC; c += kWave) {
-                    if (cstate[c] == -1) {
-                        const T v = S[(long long)r * nC + c];
+        const int ntodo = s_count[1];
+        for (int k = wave; k < ntodo; k += NW) {
+            const int x = uni(todo[k]);
+            const bool is_row = x < nR;
+            const int y0 = is_row ? x : x - nR;
+            const T* line = is_row ? S + (long long)y0 * nC : St + (long long)y0 * nR;
+            const int n = is_row ? nC : nR;
+            const int* other = is_row ? cstate : rstate;
+            T bv = T(-1);
+            int bk = INT_MAX, bi = -1;
+            for (int z0 = lane; z0 < n; z0 += 4 * kWave) {
+                T v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int z = z0 + u * kWave;
+                    v[u] = z < n ? line[z] : T(-1);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int z = z0 + u * kWave;
+                    if (z < n && other[z] == -1) {
+                        const int r = is_row ? y0 : z, c = is_row ? z : y0;
                         const int key = swp ? c * nR + r : r * nC + c;
-                        if (better(v, key, bv, bk)) {
-                            bv = v;
+                        if (better(v[u], key, bv, bk)) {
+                            bv = v[u];
                             bk = key;
-                            bc = c;
+                            bi = z;
                         }
                     }
                 }
-                wave_argmax(bv, bk, bc);
-                if (lane == 0) rbest[r] = bc;
-            } else {
-                const int c = it - nR;
-                if (uni(cstate[c]) != -1 || uni(cbest[c]) != -2) continue;
-                T bv = T(-1);
-                int bk = INT_MAX, br = -1;
-                for (int r = lane; r < nR; r += kWave) {
-                    if (rstate[r] == -1) {
-                        const T v = S[(long long)r * nC + c];
-                        const int key = swp ? c * nR + r : r * nC + c;
-                        if (better(v, key, bv, bk)) {
-                            bv = v;
-                            bk = key;
-                            br = r;
-                        }
-                    }
-                }
-                wave_argmax(bv, bk, br);
-                if (lane == 0) cbest[c] = br;
+            }
+            wave_argmax(bv, bk, bi);
+            if (lane == 0) {
+                if (is_row)
+                    rbest[y0] = bi;
+                else
+                    cbest[y0] = bi;
             }
         }
         __syncthreads();
+        if (tid == 0) s_count[1] = 0;
         for (int r = tid; r < nR; r += NT) {
             if (rstate[r] == -1) {
                 const int c = rbest[r];
@@ -321,12 +334,18 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
             }
         }
         __syncthreads();
-        // stale marks: bests that were just taken by someone else
+        // stale: free rows/columns whose best was just taken by someone else
         for (int r = tid; r < nR; r += NT)
-            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) rbest[r] = -2;
+            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) {
+                rbest[r] = -2;
+                todo[atomicAdd(s_count + 1, 1)] = r;
+            }
         for (int c = tid; c < nC; c += NT)
-            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) cbest[c] = -2;
-        const int now = *s_count;
+            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) {
+                cbest[c] = -2;
+                todo[atomicAdd(s_count + 1, 1)] = nR + c;
+            }
+        const int now = s_count[0];
         __syncthreads();
         if (now == done) break;  // no progress: only possible with non-finite S
         done = now;
@@ -407,7 +426,8 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
     else
         it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
     const T* S = reinterpret_cast<const T*>(smem + (it.final_buf ? sbytes : 0));
-    match_and_write<T, NT>(J, p, A, B, sh, S, G, it, res, red, s_count);
+    T* St = reinterpret_cast<T*>(smem + (it.final_buf ? 0 : sbytes));
+    match_and_write<T, NT>(J, p, A, B, sh, S, St, G, it, res, red, s_count);
 }
 
 template <typename T, int NT>
@@ -432,7 +452,7 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
     const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
     const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, S0, s0);
     const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, Sp, degenerate, red);
-    match_and_write<T, NT>(J, p, A, B, sh, it.final_buf ? S1 : S0, G, it, res, red, s_count);
+    match_and_write<T, NT>(J, p, A, B, sh, it.final_buf ? S1 : S0, it.final_buf ? S0 : S1, G, it, res, red, s_count);
 }
 
 // Persistent driver: one pair at a time per workgroup, pulled from the
@@ -474,8 +494,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_si
 void pair_lds_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (NT / kWave)];
-    __shared__ int s_item, s_count;
-    drive<false, T, NT, NCH>(J, smem, red, &s_item, &s_count);
+    __shared__ int s_item, s_count[2];
+    drive<false, T, NT, NCH>(J, smem, red, &s_item, s_count);
 }
 
 template <typename T>
@@ -483,8 +503,8 @@ __global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(
 void pair_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
-    __shared__ int s_item, s_count;
-    drive<true, T, kGlobalThreads, 1>(J, smem, red, &s_item, &s_count);
+    __shared__ int s_item, s_count[2];
+    drive<true, T, kGlobalThreads, 1>(J, smem, red, &s_item, s_count);
 }
 
 // Pairs no kernel can take get an INVALID_INPUT result.
