@@ -249,7 +249,7 @@ struct LargeState {
     int swap;            // state rows are A's nodes (rows = B's otherwise)
     int nR, nC;          // state shape: n_B x n_A, or M x m when resized
     int M;               // common size when resized
-    int ntiles;          // tiles of the state (32 rows x 64 columns)
+    int ntiles;          // tiles of the state (128 rows x 64 columns)
     int active;          // still iterating
     unsigned status;     // CFSIM_* bits once decided
     int final_step;      // k of the returned iterate
@@ -288,7 +288,7 @@ struct LargeJob {
 constexpr int kLargeMaxNodes = 8192;  // bound of the finish kernel's LDS matching state
 // Bytes of one node record of the tiled path (first 2 successors, 3 predecessors).
 __host__ __device__ inline size_t large_rec_bytes(int esize) { return esize == 8 ? 80 : 48; }
-__host__ __device__ inline long long large_tiles(int n) { return (long long)((n + 31) / 32) * ((n + 63) / 64); }
+__host__ __device__ inline long long large_tiles(int n) { return (long long)((n + 127) / 128) * ((n + 63) / 64); }
 int large_step_grid(int num_cus);
 int set_large_attributes();
 int launch_large(int dtype, const LargeJob& job, int grid, hipStream_t stream);

@@ -40,10 +40,11 @@ using dev::uni;
 using dev::wave_argmax;
 using dev::wave_sum;
 
-constexpr int kTileRows = 32;                   // rows per tile
-constexpr int kStepThreads = 256;               // 4 waves, 8 rows each
+constexpr int kTileRows = 128;                  // rows per tile
+constexpr int kStepThreads = 256;               // 4 waves, 32 rows each
 constexpr int kNWStep = kStepThreads / kWave;
 constexpr int kRowsPerWave = kTileRows / kNWStep;
+constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
 constexpr int kFinishThreads = 1024;
 constexpr int kLS = 2;                          // successors per lane column in registers
 constexpr int kLP = 3;                          // predecessors per lane column in registers
@@ -52,7 +53,7 @@ constexpr int kSlotV = 4;                       // resize: V
 constexpr int kSlotS = 5;                       // resize: expanded final S
 
 __device__ inline int tiles_of(int nC, int nR) { return ((nR + kTileRows - 1) / kTileRows) * ((nC + 63) / 64); }
-static_assert(kTileRows == 32, "large_tiles() in cfsim_internal.h assumes 32-row tiles");
+static_assert(kTileRows == 128, "large_tiles() in cfsim_internal.h assumes 128-row tiles");
 
 // Pair p's buffer b of slot_elems elements.
 template <typename T>
@@ -401,6 +402,54 @@ __device__ inline T row_terms(const T* src, int nC, const int (&ru)[kLS], const 
     return acc;
 }
 
+// All first-slot terms of one row, padded (zero weights read row 0): the code
+// is the same for every row, so the gathers of several rows can be issued
+// before any of them is used.
+template <typename T>
+__device__ inline T row_padded(const T* src, int nC, const NodeRec<T>& r, const NodeRec<T>& c) {
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < kLS; ++a) {
+        const T* row = src + (long long)uni(r.su[a]) * nC;
+        T in = c.sw[0] * row[c.su[0]];
+#pragma unroll
+        for (int q = 1; q < kLS; ++q) in = dev::fma_t(c.sw[q], row[c.su[q]], in);
+        acc = dev::fma_t(uni(r.sw[a]), in, acc);
+    }
+#pragma unroll
+    for (int b = 0; b < kLP; ++b) {
+        const T* row = src + (long long)uni(r.pu[b]) * nC;
+        T in = c.pw[0] * row[c.pu[0]];
+#pragma unroll
+        for (int q = 1; q < kLP; ++q) in = dev::fma_t(c.pw[q], row[c.pu[q]], in);
+        acc = dev::fma_t(uni(r.pw[b]), in, acc);
+    }
+    return acc;
+}
+
+// Terms of row i past its first kLS successors / kLP predecessors (CSR lists).
+template <typename T>
+__device__ inline T row_rest(const T* src, int nC, const GraphRef& Rg, int i, const NodeRec<T>& c) {
+    T acc = T(0);
+    const int e1 = uni(Rg.rp[i + 1]);
+    for (int e = uni(Rg.rp[i]) + kLS; e < e1; ++e) {
+        const T* row = src + (long long)uni(Rg.ci[e]) * nC;
+        T in = T(0);
+#pragma unroll
+        for (int q = 0; q < kLS; ++q) in = dev::fma_t(c.sw[q], row[c.su[q]], in);
+        acc = dev::fma_t(T(Rg.w[e]), in, acc);
+    }
+    const int f1 = uni(Rg.cp[i + 1]);
+    for (int e = uni(Rg.cp[i]) + kLP; e < f1; ++e) {
+        const T* row = src + (long long)uni(Rg.ri[e]) * nC;
+        T in = T(0);
+#pragma unroll
+        for (int q = 0; q < kLP; ++q) in = dev::fma_t(c.pw[q], row[c.pu[q]], in);
+        acc = dev::fma_t(T(Rg.w[uni(Rg.eid[e])]), in, acc);
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------- the operator
 // Launch k (1 .. max_iter): X_k = M_{Rg,Cg}(src) * sigma_{k-1} over the state
 // (nR x nC).  Plain pairs: src = Y_{k-1} (S_0 is the constant
@@ -411,6 +460,7 @@ __device__ inline T row_terms(const T* src, int nC, const int (&ru)[kLS], const 
 template <typename T>
 __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
     __shared__ double red[2 * kNWStep];
+    __shared__ NodeRec<T> trec[kTileRows];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const bool compute = k <= J.max_iter;
     const bool want_delta = (k & 1) && k >= 3;
@@ -449,6 +499,64 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         }
         double nu2 = 0.0, d2 = 0.0;
         const int i0 = tl.r0 + wave * kRowsPerWave;
+        if (compute && !first && !ovf) {
+            // the wave's row records, staged in LDS (rows past the end get
+            // an empty record); then rows in groups of kUnroll, all of a
+            // group's gathers issued before any is used
+            if (lane < kRowsPerWave) {
+                NodeRec<T> r{};
+                if (i0 + lane < nR) r = rrec[i0 + lane];
+                trec[wave * kRowsPerWave + lane] = r;
+            }
+            bool long_rows = false;
+#pragma unroll 1
+            for (int g = 0; g < kRowsPerWave; g += kUnroll) {
+                T acc[kUnroll];
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    acc[u] = row_padded<T>(src, nC, trec[wave * kRowsPerWave + g + u], cr);
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const NodeRec<T>& r = trec[wave * kRowsPerWave + g + u];
+                    long_rows |= uni(r.ns) > kLS || uni(r.np) > kLP;
+                }
+                if (long_rows) {
+                    GraphRef Rg2, Cg2;
+                    state_graphs(J, p, s, &Rg2, &Cg2);
+#pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        const NodeRec<T>& r = trec[wave * kRowsPerWave + g + u];
+                        if (uni(r.ns) > kLS || uni(r.np) > kLP) acc[u] += row_rest<T>(src, nC, Rg2, i0 + g + u, cr);
+                    }
+                    long_rows = false;
+                }
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int i = i0 + g + u;
+                    const T v = acc[u] * sig;
+                    if (i < nR && colv) {
+                        dst[(long long)i * nC + j] = v;
+                        nu2 += (double)v * (double)v;
+                    }
+                }
+            }
+            if (!rz && want_delta) {
+                for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                    const int i = i0 + rr;
+                    if (i >= nR) break;
+                    if (colv) {
+                        const long long o = (long long)i * nC + j;
+                        const T a = T(src[o] * sig);
+                        const T b = old_is_s0 ? c0v : T(old[o] * sig3);
+                        const double d = (double)a - (double)b;
+                        d2 += d * d;
+                    }
+                }
+            }
+            if (rz) continue;
+            tile_partials(J, t, nu2, d2, red);
+            continue;
+        }
         NodeRec<T> nxt = rrec[min(i0, nR - 1)];
         for (int rr = 0; rr < kRowsPerWave; ++rr) {
             const int i = i0 + rr;
