@@ -132,12 +132,12 @@ int lds_blocks_per_cu(int v, int esize) {
 
 int num_cus_of(const cfsim_context* ctx) { return ctx && ctx->num_cus > 0 ? ctx->num_cus : 256; }
 
-// Elements of one global-kernel slot (each of S_cur, S_next, S_{k-2}).
+// Elements of one global-kernel slot (each of the two iterate buffers).
 long long global_slot_elems(int max_nodes) { return (long long)max_nodes * (long long)max_nodes; }
 
 // Batch workspace: order[n_pairs] | bounds[2*kBuckets] | queues[kBuckets]
-//   | per LDS variant v: grid slots of variant_slot_elems(v) (S_{k-2})
-//   | global kernel: grid slots of 3 * global_slot_elems
+//   | global kernel: grid slots of 2 * global_slot_elems (the LDS variants
+//     keep both iterates in LDS and need no slots)
 struct BatchWs {
     int32_t* order;
     int32_t* bounds;
@@ -146,8 +146,8 @@ struct BatchWs {
 };
 size_t slot_bytes(const cfsim_context* ctx, int v, int esize, int max_nodes) {
     const size_t wgs = (size_t)num_cus_of(ctx) * (size_t)lds_blocks_per_cu(v, esize);
-    if (v == cfsim::kBucketGlobal) return align256(wgs * 3 * (size_t)global_slot_elems(max_nodes) * esize);
-    return align256(wgs * (size_t)cfsim::variant_slot_elems(v, esize) * esize);
+    if (v == cfsim::kBucketGlobal) return align256(wgs * 2 * (size_t)global_slot_elems(max_nodes) * esize);
+    return 0;
 }
 size_t batch_ws_bytes(const cfsim_context* ctx, int64_t n_pairs, int esize, int max_nodes) {
     size_t b = align256((size_t)n_pairs * 4) + align256(2 * cfsim::kBuckets * 4) + align256(cfsim::kBuckets * 4);
@@ -422,8 +422,8 @@ size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t
     if (n_a < 1 || n_b < 1 || !opt) return 0;
     const size_t esize = esize_of(opt->dtype);
     if (opt->resize == CFSIM_RESIZE_BILINEAR) return large_ws_bytes(1, n_a > n_b ? n_a : n_b, (int)esize, 6);
-    // S_{k-2} slot (LDS kernels) or S_cur, S_next, S_{k-2} (global kernel)
-    return align256(3 * (size_t)n_a * (size_t)n_b * esize);
+    // the two iterate buffers of the global kernel (the LDS kernels need none)
+    return align256(2 * (size_t)n_a * (size_t)n_b * esize);
 }
 
 cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B, const cfsim_options* opt,
@@ -532,8 +532,8 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
         job.variant = v;
         int grid = 1;
         if (v < cfsim::kNumVariants) {
-            job.gws = b.slots[v];
-            job.slot_elems = cfsim::variant_slot_elems(v, esize);
+            job.gws = nullptr;  // both iterates stay in LDS
+            job.slot_elems = 0;
             grid = ctx->grid[d][v];
         } else if (v == cfsim::kBucketGlobal) {
             job.gws = b.slots[v];

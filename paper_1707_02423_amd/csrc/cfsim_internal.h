@@ -80,12 +80,6 @@ __host__ __device__ inline Variant variant_info(int v, int esize) {
     }
 }
 
-// Elements of the per-workgroup S_{k-2} slot an LDS variant needs (the most
-// entries two S buffers of its LDS budget can hold).
-__host__ __device__ inline long long variant_slot_elems(int v, int esize) {
-    return (long long)variant_info(v, esize).lds_bytes / (2 * esize);
-}
-
 __host__ __device__ inline size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 __host__ __device__ inline PairShape make_shape(int nA, int nB, int swap, int NW) {
@@ -121,8 +115,8 @@ __host__ __device__ inline size_t lds_pair_bytes(const PairShape& s, int nnzR, i
     return 2 * align16((size_t)s.nR * s.nC * esize) + lds_lists_bytes(s.nR, s.nC, nnzR, nnzC, esize);
 }
 
-// The global-memory kernel: one workgroup per pair, S_cur, S_next and S_{k-2}
-// in a workspace slot of `slot_elems` elements each; lists in LDS.
+// The global-memory kernel: one workgroup per pair, S_cur and S_next in a
+// workspace slot of `slot_elems` elements each; lists in LDS.
 constexpr int kGlobalThreads = 512;
 constexpr int kGlobalLds = 78 * 1024;
 
@@ -185,8 +179,8 @@ struct PairJob {
     void* S_out;
     const int64_t* S_off;
     int variant;
-    // Workspace of gridDim.x slots of slot_elems elements each: S_{k-2} (LDS
-    // kernel), or S_cur, S_next, S_{k-2} at 3 * slot_elems (global kernel).
+    // Global kernel: gridDim.x slots of S_cur, S_next (2 * slot_elems
+    // elements each); unused by the LDS kernels.
     void* gws;
     long long slot_elems;
 };

@@ -16,8 +16,7 @@
 // weights) sit in VGPRs for the whole pair; longer lists add an overflow pass
 // reading the staged C lists.  Y goes to the second buffer un-normalised;
 // ||Y||^2 is reduced in FP64 in a fixed order and 1/||Y|| is folded into the
-// next update (odd k) or applied in place with the even-step test (even k),
-// which keeps S_{k-2} in VGPRs.
+// next update; the even-step test needs no third buffer (see EvenSums).
 //
 // Matching: greedy in the order (value desc, original flat index asc) equals
 // the locally-dominant matching for a strict total order, so it runs in
@@ -35,43 +34,78 @@ namespace {
 
 using namespace dev;
 
-// Even step: S_k = S * inv in place, d2 = ||S_k - S_{k-2}||^2 (FP64, each
-// thread in index order), S_{k-2} := S_k.  Loads are taken in batches of
-// eight before any store, so the S_{k-2} reads (global memory when it does not
-// fit LDS) overlap instead of waiting one by one.
-template <typename T, int NT>
-__device__ inline double normalise_step(T* S, T* Sp, long long total, T inv) {
-    constexpr int B = 8;
-    double d2 = 0.0;
-    for (long long t0 = threadIdx.x; t0 < total; t0 += B * NT) {
-        T a[B], b[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const long long t = t0 + u * NT;
-            a[u] = t < total ? S[t] : T(0);
-            b[u] = t < total ? Sp[t] : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const long long t = t0 + u * NT;
-            if (t < total) {
-                const T sv = a[u] * inv;
-                const double d = (double)sv - (double)b[u];
-                S[t] = sv;
-                Sp[t] = sv;
-                d2 += d * d;
-            }
-        }
-    }
-    return d2;
+// The kernel's argument block, read anew through a pointer the compiler cannot
+// see through: values it loaded from the block before are not reused, so none
+// of them is held in registers across a pair's iteration (which needs every
+// register it can get to keep its LDS reads in flight).  The block holds the
+// one PairJob argument of the pair kernels at offset 0.
+__device__ inline const PairJob& job_args() {
+    auto p = __builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return *(const PairJob*)p;
 }
 
-// Steps a4-a6 with S in LDS (NCH = exact chunk count); S_{k-2} lives in a
-// third LDS buffer Sp_lds when the variant's budget holds it, else in the
-// workgroup's global slot Sp.  Returns the buffer holding the final S.
+// The even-step test without a stored S_{k-2}.  The buffers only ever hold
+// un-normalised iterates Y_j (S_j = Y_j / nu_j), and an even update k writes
+// Y_k over the buffer that holds Y_{k-2}.  Each thread reads the old value of
+// every entry it is about to write, so with dy = Y_k - Y_{k-2}, a = 1/nu_{k-2}
+// (1 for k = 2, whose S_0 is stored as is) and b = 1/nu_k - a,
+//   S_k - S_{k-2} = a dy + b Y_k,
+//   ||S_k - S_{k-2}||^2 = a^2 sum dy^2 + 2ab sum dy Y_k + b^2 nu_k^2,
+// three FP64 sums taken in the same pass as nu_k^2.  Near convergence dy and b
+// are both of the order of the step, so the three terms are small and do not
+// cancel from O(1) magnitudes; every entry's difference is formed before any
+// squaring, as the direct definition does.
+struct EvenSums {
+    double nu2, dy2, dyy;
+};
+
+// Block reduction of the three even-step sums (red holds 3 * NW doubles).
+template <int NW>
+__device__ inline EvenSums block_sum_even(EvenSums s, double* red) {
+    s.nu2 = wave_sum(s.nu2);
+    s.dy2 = wave_sum(s.dy2);
+    s.dyy = wave_sum(s.dyy);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const int w = threadIdx.x / kWave;
+        red[w] = s.nu2;
+        red[NW + w] = s.dy2;
+        red[2 * NW + w] = s.dyy;
+    }
+    __syncthreads();
+    EvenSums t{0.0, 0.0, 0.0};
+    for (int w = 0; w < NW; ++w) {
+        t.nu2 += red[w];
+        t.dy2 += red[NW + w];
+        t.dyy += red[2 * NW + w];
+    }
+    return t;
+}
+
+// ||S_k - S_{k-2}|| from the even-step sums (a = 1/nu_{k-2}, inv = 1/nu_k).
+__device__ inline double even_step_delta(const EvenSums& t, double a, double inv) {
+    const double b = inv - a;
+    const double d2 = a * a * t.dy2 + 2.0 * a * b * t.dyy + b * b * t.nu2;
+    return sqrt(fmax(d2, 0.0));
+}
+
+// Per-entry part of the even-step sums: y_new is the entry written, y_old the
+// value it replaces.
+template <typename T>
+__device__ __forceinline__ void even_terms(EvenSums& s, T y_new, T y_old) {
+    const double v = (double)y_new;
+    const double dy = v - (double)y_old;
+    s.dy2 += dy * dy;
+    s.dyy += dy * v;
+}
+
+// Steps a4-a6 with S in LDS (NCH = exact chunk count).  The two buffers hold
+// un-normalised iterates; 1/nu of the stored one (sigma) is folded into the
+// next update and applied in place once, at the end.  Returns the buffer
+// holding the final S.
 template <typename T, int NT, int NCH>
 __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
-                               const Lists<T>& G, bool degenerate, T* Sp, T* Sp_lds, double* red) {
+                               const Lists<T>& G, bool degenerate, double* red) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
     const int nR = sh.nR, nC = sh.nC;
@@ -94,60 +128,66 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
         out.status = CFSIM_DEGENERATE;
         return out;
     }
-    const unsigned char* Sb = smem;     // S_{k-1} (times sigma)
-    unsigned char* Nb = smem + sbytes;  // update target
+    const unsigned char* Sb = smem;     // Y_{k-1} (S_{k-1} = sigma * Y_{k-1})
+    unsigned char* Nb = smem + sbytes;  // update target, holds Y_{k-2}
     int cur = 0;
     T sigma = T(1);
+    double a_even = 1.0;  // 1/nu of the last even iterate (S_0 is stored normalised)
     const int last = nR - 1;
     for (int k = 1; k <= J.max_iter; ++k) {
-        double nu2 = 0.0;
+        const bool even = (k & 1) == 0;
+        EvenSums es{0.0, 0.0, 0.0};
         RowRec<T> nxt = G.rec[min(wave, last)];
         for (int i = wave; i < nR; i += NW) {
             const RowRec<T> rr = nxt;
             nxt = G.rec[min(i + NW, last)];  // prefetch the wave's next row
+            T* dst = reinterpret_cast<T*>(Nb + i * rowb);
+            T old[NCH];
+            if (even) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) old[ch] = cv[ch] ? dst[col[ch]] : T(0);
+            }
             T y[NCH];
             update_row<T, NCH>(Sb, rowb, i, rr, G, L, ovf, any_ovf, col, cv, y);
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) {
                 const T v = y[ch] * sigma;
                 if (cv[ch]) {
-                    *reinterpret_cast<T*>(Nb + i * rowb + col[ch] * esz) = v;
-                    nu2 += (double)v * (double)v;
+                    dst[col[ch]] = v;
+                    es.nu2 += (double)v * (double)v;
+                    if (even) even_terms(es, v, old[ch]);
                 }
             }
         }
-        const double tot = block_sum<NW>(nu2, red + (k & 1) * NW);
+        double tot;
+        if (even)
+            es = block_sum_even<NW>(es, red);
+        tot = even ? es.nu2 : block_sum<NW>(es.nu2, red + 3 * NW);
         if (!(tot > 0.0) || !isfinite(tot)) {  // cannot normalise: keep S_{k-1}
             out.status = CFSIM_DEGENERATE;
             break;
         }
         out.nu = sqrt(tot);
         out.iters = k;
-        const T inv = T(1.0 / out.nu);
+        const double inv = 1.0 / out.nu;
+        sigma = T(inv);
         {
             const unsigned char* t = Sb;
             Sb = Nb;
             Nb = const_cast<unsigned char*>(t);
             cur ^= 1;
         }
-        if (k & 1) {
-            sigma = inv;
-            continue;
-        }
-        // even k: normalise in place and take the step against S_{k-2}
-        // (every entry is final after the barrier above: flat, unrolled loops)
-        T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
-        const double d2 = Sp_lds ? normalise_step<T, NT>(Sw, Sp_lds, nR * nC, inv)
-                                 : normalise_step<T, NT>(Sw, Sp, nR * nC, inv);
-        sigma = T(1);
-        out.delta = sqrt(block_sum<NW>(d2, red + 2 * NW));
-        if (out.delta < J.tol) {
-            out.status = CFSIM_CONVERGED;
-            break;
+        if (even) {
+            out.delta = even_step_delta(es, a_even, inv);
+            a_even = inv;
+            if (out.delta < J.tol) {
+                out.status = CFSIM_CONVERGED;
+                break;
+            }
         }
     }
     if (out.status == 0) out.status = CFSIM_HIT_MAX_ITER;
-    if (sigma != T(1)) {  // stopped after an odd update: normalise
+    if (sigma != T(1)) {  // S = sigma * Y: every thread scales what it reads next
         T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
         for (int t = threadIdx.x; t < nR * nC; t += NT) Sw[t] *= sigma;
     }
@@ -155,11 +195,12 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
     return out;
 }
 
-// Steps a4-a6 with S_cur, S_next and S_{k-2} in global memory (one slot per
-// workgroup, L2/MALL resident while the pair runs).  Chunks are processed one
-// after the other, each with its lane lists reloaded from LDS.
+// Steps a4-a6 with both iterates in global memory (one slot per workgroup,
+// L2/MALL resident while the pair runs).  Chunks are processed one after the
+// other, each with its lane lists reloaded from LDS.  Same even-step sums and
+// folding as the LDS kernel.
 template <typename T, int NT>
-__device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const Lists<T>& G, T* S0, T* S1, T* Sp,
+__device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const Lists<T>& G, T* S0, T* S1,
                                   bool degenerate, double* red) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
@@ -173,14 +214,15 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
         out.status = CFSIM_DEGENERATE;
         return out;
     }
-    for (long long t = threadIdx.x; t < total; t += NT) Sp[t] = S0[t];
     const unsigned char* Sb = reinterpret_cast<const unsigned char*>(S0);
     unsigned char* Nb = reinterpret_cast<unsigned char*>(S1);
     int cur = 0;
     T sigma = T(1);
+    double a_even = 1.0;
     const int last = nR - 1;
     for (int k = 1; k <= J.max_iter; ++k) {
-        double nu2 = 0.0;
+        const bool even = (k & 1) == 0;
+        EvenSums es{0.0, 0.0, 0.0};
         for (int ch = 0; ch < nchunk; ++ch) {
             LaneList<T> L[1];
             int col[1];
@@ -191,40 +233,42 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
             for (int i = wave; i < nR; i += NW) {
                 const RowRec<T> rr = nxt;
                 nxt = G.rec[min(i + NW, last)];
+                T* dst = reinterpret_cast<T*>(Nb + (long long)i * rowb);
+                const T old = (even && cv[0]) ? dst[col[0]] : T(0);
                 T y[1];
                 update_row<T, 1>(Sb, rowb, i, rr, G, L, ovf, ovf[0] != 0, col, cv, y, ch);
                 const T v = y[0] * sigma;
                 if (cv[0]) {
-                    *reinterpret_cast<T*>(Nb + (long long)i * rowb + col[0] * esz) = v;
-                    nu2 += (double)v * (double)v;
+                    dst[col[0]] = v;
+                    es.nu2 += (double)v * (double)v;
+                    if (even) even_terms(es, v, old);
                 }
             }
         }
-        const double tot = block_sum<NW>(nu2, red + (k & 1) * NW);
+        if (even)
+            es = block_sum_even<NW>(es, red);
+        const double tot = even ? es.nu2 : block_sum<NW>(es.nu2, red + 3 * NW);
         if (!(tot > 0.0) || !isfinite(tot)) {
             out.status = CFSIM_DEGENERATE;
             break;
         }
         out.nu = sqrt(tot);
         out.iters = k;
-        const T inv = T(1.0 / out.nu);
+        const double inv = 1.0 / out.nu;
+        sigma = T(inv);
         {
             const unsigned char* t = Sb;
             Sb = Nb;
             Nb = const_cast<unsigned char*>(t);
             cur ^= 1;
         }
-        if (k & 1) {
-            sigma = inv;
-            continue;
-        }
-        T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
-        const double d2 = normalise_step<T, NT>(Sw, Sp, total, inv);
-        sigma = T(1);
-        out.delta = sqrt(block_sum<NW>(d2, red + 2 * NW));
-        if (out.delta < J.tol) {
-            out.status = CFSIM_CONVERGED;
-            break;
+        if (even) {
+            out.delta = even_step_delta(es, a_even, inv);
+            a_even = inv;
+            if (out.delta < J.tol) {
+                out.status = CFSIM_CONVERGED;
+                break;
+            }
         }
     }
     if (out.status == 0) out.status = CFSIM_HIT_MAX_ITER;
@@ -393,41 +437,46 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
 
 template <typename T, int NT, int NCHMAX>
 __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+    IterOut it;
+    {
+        GraphRef A{}, B{};
+        cfsim_pair_result* res;
+        PairShape sh{};
+        const bool ok = resolve_graphs(J, p, A, B, res) &&
+                        choose_shape(A.n, B.n, A.nnz, B.nnz, J.variant, (int)sizeof(T), &sh) && sh.nchunk <= NCHMAX;
+        if (!ok) {
+            if (threadIdx.x == 0) write_invalid(res);
+            return;
+        }
+        const GraphRef R = sh.swap ? A : B;
+        const GraphRef C = sh.swap ? B : A;
+        const int nR = sh.nR, nC = sh.nC;
+        const size_t sbytes = align16((size_t)nR * nC * sizeof(T));
+        const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
+        const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
+        const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
+        if (NCHMAX == 1 || sh.nchunk == 1)
+            it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red);
+        else if (NCHMAX == 2 || sh.nchunk == 2)
+            it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, red);
+        else
+            it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red);
+    }
+    // The pair's graphs, shape and lists again, from fresh reads of the
+    // arguments (the same values: the iteration does not change them).
+    const PairJob& Jr = job_args();
     GraphRef A{}, B{};
     cfsim_pair_result* res;
     PairShape sh{};
-    const bool ok = resolve_graphs(J, p, A, B, res) &&
-                    choose_shape(A.n, B.n, A.nnz, B.nnz, J.variant, (int)sizeof(T), &sh) && sh.nchunk <= NCHMAX &&
-                    (long long)A.n * B.n <= J.slot_elems;
-    if (!ok) {
-        if (threadIdx.x == 0) write_invalid(res);
-        return;
-    }
+    resolve_graphs(Jr, p, A, B, res);
+    choose_shape(A.n, B.n, A.nnz, B.nnz, Jr.variant, (int)sizeof(T), &sh);
     const GraphRef R = sh.swap ? A : B;
     const GraphRef C = sh.swap ? B : A;
-    const int nR = sh.nR, nC = sh.nC;
-    const size_t sbytes = align16((size_t)nR * nC * sizeof(T));
-    const size_t lbytes = lds_lists_bytes(nR, nC, R.nnz, C.nnz, (int)sizeof(T));
-    const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
-    const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
-    // S_{k-2}: third LDS buffer if it fits the variant's budget, else the global slot
-    T* Sp_lds = (3 * sbytes + lbytes <= (size_t)variant_info(J.variant, (int)sizeof(T)).lds_bytes)
-                    ? reinterpret_cast<T*>(smem + 2 * sbytes + align16(lbytes))
-                    : nullptr;
-    T* Sp = reinterpret_cast<T*>(J.gws) + (size_t)blockIdx.x * (size_t)J.slot_elems;
-    T* Spi = Sp_lds ? Sp_lds : Sp;
-    for (int t = threadIdx.x; t < nR * nC; t += NT) Spi[t] = s0;
-    const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
-    IterOut it;
-    if (sh.nchunk == 1)
-        it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
-    else if (NCHMAX >= 2 && sh.nchunk == 2)
-        it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
-    else
-        it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, Sp, Sp_lds, red);
+    const size_t sbytes = align16((size_t)sh.nR * sh.nC * sizeof(T));
+    const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, sh.nR, sh.nC, R.nnz, C.nnz);
     const T* S = reinterpret_cast<const T*>(smem + (it.final_buf ? sbytes : 0));
     T* St = reinterpret_cast<T*>(smem + (it.final_buf ? 0 : sbytes));
-    match_and_write<T, NT>(J, p, A, B, sh, S, St, G, it, res, red, s_count);
+    match_and_write<T, NT>(Jr, p, A, B, sh, S, St, G, it, res, red, s_count);
 }
 
 template <typename T, int NT>
@@ -445,13 +494,12 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
     const GraphRef C = sh.swap ? B : A;
     const int nR = sh.nR, nC = sh.nC;
     const Lists<T> G = carve_lists<T>(smem, nR, nC, R.nnz, C.nnz);
-    T* slot = reinterpret_cast<T*>(J.gws) + (size_t)blockIdx.x * 3 * (size_t)J.slot_elems;
+    T* slot = reinterpret_cast<T*>(J.gws) + (size_t)blockIdx.x * 2 * (size_t)J.slot_elems;
     T* S0 = slot;
     T* S1 = slot + J.slot_elems;
-    T* Sp = slot + 2 * J.slot_elems;
     const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
     const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, S0, s0);
-    const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, Sp, degenerate, red);
+    const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, degenerate, red);
     match_and_write<T, NT>(J, p, A, B, sh, it.final_buf ? S1 : S0, it.final_buf ? S0 : S1, G, it, res, red, s_count);
 }
 
@@ -468,17 +516,17 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
         }
         return;
     }
-    const int begin = J.bounds[0], end = J.bounds[1];
     for (;;) {
-        if (threadIdx.x == 0) *s_item = begin + atomicAdd(J.queue, 1);
+        const PairJob& Jl = job_args();
+        if (threadIdx.x == 0) *s_item = Jl.bounds[0] + atomicAdd(Jl.queue, 1);
         __syncthreads();
         const int item = *s_item;
         __syncthreads();
-        if (item >= end) break;
+        if (item >= Jl.bounds[1]) break;
         if constexpr (GLOBAL)
-            global_pair<T, NT>(J, J.order[item], smem, red, s_count);
+            global_pair<T, NT>(Jl, Jl.order[item], smem, red, s_count);
         else
-            lds_pair<T, NT, NCH>(J, J.order[item], smem, red, s_count);
+            lds_pair<T, NT, NCH>(Jl, Jl.order[item], smem, red, s_count);
     }
 }
 

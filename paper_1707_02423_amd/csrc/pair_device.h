@@ -183,22 +183,60 @@ __device__ inline T lane_term(const unsigned char* Sb, int uo, T w, const int (&
     return fma_t(w, a, y);
 }
 
+// Chunks whose S reads are issued together (more would spill registers).
+template <typename T>
+constexpr int chunks_per_phase() {
+    return sizeof(T) == 8 ? 1 : 2;
+}
+
 // Row update specialised on the row's successor / predecessor counts: every
-// S read of the row (all chunks) is independent of the others.
+// S read of a phase is independent of the others, so all of them are issued
+// before the first is used; the scheduling barrier keeps the compiler from
+// interleaving them with the arithmetic to save registers, which would leave
+// each pair of reads waiting out the LDS latency on its own.
 template <typename T, int NCH, int NS, int NP>
 __device__ inline void row_fixed(const unsigned char* Sb, const int (&su)[kDS], const T (&sw)[kDS],
                                  const int (&pu)[kDP], const T (&pw)[kDP], const LaneList<T> (&L)[NCH],
                                  T (&y)[NCH]) {
+    constexpr int CG = NCH < chunks_per_phase<T>() ? NCH : chunks_per_phase<T>();
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
+    for (int c0 = 0; c0 < NCH; c0 += CG) {
+        // the phase's S reads are all issued before the arithmetic that uses them
+        T xs[NS > 0 ? NS : 1][CG][kDS], xp[NP > 0 ? NP : 1][CG][kDP];
 #pragma unroll
-    for (int a = 0; a < NS; ++a)
+        for (int a = 0; a < NS; ++a)
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDS>(Sb, su[a], sw[a], L[ch].sv, L[ch].sw, y[ch]);
+            for (int c = 0; c < CG; ++c)
 #pragma unroll
-    for (int b = 0; b < NP; ++b)
+                for (int q = 0; q < kDS; ++q) xs[a][c][q] = lds_at<T>(Sb, su[a] + L[c0 + c].sv[q]);
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) y[ch] = lane_term<T, kDP>(Sb, pu[b], pw[b], L[ch].pv, L[ch].pw, y[ch]);
+        for (int b = 0; b < NP; ++b)
+#pragma unroll
+            for (int c = 0; c < CG; ++c)
+#pragma unroll
+                for (int q = 0; q < kDP; ++q) xp[b][c][q] = lds_at<T>(Sb, pu[b] + L[c0 + c].pv[q]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            const LaneList<T>& l = L[c0 + c];
+            T acc = T(0);
+#pragma unroll
+            for (int a = 0; a < NS; ++a) {
+                T t = l.sw[0] * xs[a][c][0];
+#pragma unroll
+                for (int q = 1; q < kDS; ++q) t = fma_t(l.sw[q], xs[a][c][q], t);
+                acc = fma_t(sw[a], t, acc);
+            }
+#pragma unroll
+            for (int b = 0; b < NP; ++b) {
+                T t = l.pw[0] * xp[b][c][0];
+#pragma unroll
+                for (int q = 1; q < kDP; ++q) t = fma_t(l.pw[q], xp[b][c][q], t);
+                acc = fma_t(pw[b], t, acc);
+            }
+            y[c0 + c] = acc;
+        }
+    }
 }
 
 // Rows with longer lists: loops over the staged R edges.

@@ -96,7 +96,7 @@ def test_score_validation(case, code, text):
 def test_score_workspace_size():
     L = cf.lib()
     opt = cf.options("f32")
-    assert L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >= 3 * 12 * 16 * 4
+    assert L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >= 2 * 12 * 16 * 4
     assert L.cfsim_score_workspace_size(None, 0, 16, ctypes.byref(opt)) == 0
 
 
