@@ -36,6 +36,7 @@ namespace cfsim {
 namespace {
 
 using dev::better;
+using dev::scan_start;
 using dev::uni;
 using dev::wave_argmax;
 using dev::wave_sum;
@@ -816,7 +817,7 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
             const int n = is_row ? nC : nR;
             const int* other = is_row ? cstate : rstate;
             const int kb = is_row ? x * nC : x, ks = is_row ? 1 : nC;
-            T bv = T(-1);
+            T bv = scan_start<T>();
             int bk = INT_MAX, bi = -1;
             for (int y0 = lane; y0 < n; y0 += 8 * kWave) {
                 T v[8];
@@ -864,7 +865,7 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
             if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) cbest[c] = -2;
         const int now = s_count;
         __syncthreads();
-        if (now == done) break;  // no progress: only possible with non-finite S
+        if (now == done) break;  // guard: the earliest free entry is always a mutual best
         done = now;
     }
 

@@ -9,8 +9,8 @@
 // columns l, l+64, ...  An entry of the update is the direct double sum
 //   Y[i][j] = sum_{u in succ_R(i)} w_iu sum_{v in succ_C(j)} w_jv S[u][v]
 //           + sum_{u in pred_R(i)} w_ui sum_{v in pred_C(j)} w_vj S[u][v].
-// The R side is wave-uniform: a row's edge lists are broadcast from LDS into
-// SGPRs and the code is specialised on the row's (successor, predecessor)
+// The R side is wave-uniform: a row's record is broadcast from LDS to every
+// lane and the code is specialised on the row's (successor, predecessor)
 // counts, so every S read of a row is issued back to back.  The C side is per
 // lane: the lane's first 2 successors and 3 predecessors (padded with zero
 // weights) sit in VGPRs for the whole pair; longer lists add an overflow pass
@@ -99,6 +99,36 @@ __device__ __forceinline__ void even_terms(EvenSums& s, T y_new, T y_old) {
     s.dyy += dy * v;
 }
 
+// One update's rows of a wave: Y = (B S A^T + B^T S A) * sigma into Nb, with
+// nu^2 and, on even updates (EVEN), the even-step sums.
+template <bool EVEN, typename T, int NT, int NCH>
+__device__ __forceinline__ void lds_rows(const unsigned char* Sb, unsigned char* Nb, int rowb, int nR, const Lists<T>& G,
+                                         const LaneList<T> (&L)[NCH], const uint64_t (&ovf)[NCH], bool any_ovf,
+                                         const int (&col)[NCH], const bool (&cv)[NCH], T sigma, EvenSums& es) {
+    constexpr int NW = NT / kWave;
+    const int wave = uni((int)threadIdx.x / kWave);
+    for (int i = wave; i < nR; i += NW) {
+        const RowRec<T> rr = G.rec[i];
+        T* dst = reinterpret_cast<T*>(Nb + i * rowb);
+        T old[NCH];
+        if constexpr (EVEN) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) old[ch] = cv[ch] ? dst[col[ch]] : T(0);
+        }
+        T y[NCH];
+        update_row<T, NCH>(Sb, rowb, i, rr, G, L, ovf, any_ovf, col, cv, y);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const T v = y[ch] * sigma;
+            if (cv[ch]) {
+                dst[col[ch]] = v;
+                es.nu2 += (double)v * (double)v;
+                if constexpr (EVEN) even_terms(es, v, old[ch]);
+            }
+        }
+    }
+}
+
 // Steps a4-a6 with S in LDS (NCH = exact chunk count).  The two buffers hold
 // un-normalised iterates; 1/nu of the stored one (sigma) is folded into the
 // next update and applied in place once, at the end.  Returns the buffer
@@ -107,7 +137,6 @@ template <typename T, int NT, int NCH>
 __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
                                const Lists<T>& G, bool degenerate, double* red) {
     constexpr int NW = NT / kWave;
-    const int wave = uni((int)threadIdx.x / kWave);
     const int nR = sh.nR, nC = sh.nC;
     const int esz = (int)sizeof(T);
     const int rowb = nC * esz;
@@ -133,32 +162,13 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
     int cur = 0;
     T sigma = T(1);
     double a_even = 1.0;  // 1/nu of the last even iterate (S_0 is stored normalised)
-    const int last = nR - 1;
     for (int k = 1; k <= J.max_iter; ++k) {
         const bool even = (k & 1) == 0;
         EvenSums es{0.0, 0.0, 0.0};
-        RowRec<T> nxt = G.rec[min(wave, last)];
-        for (int i = wave; i < nR; i += NW) {
-            const RowRec<T> rr = nxt;
-            nxt = G.rec[min(i + NW, last)];  // prefetch the wave's next row
-            T* dst = reinterpret_cast<T*>(Nb + i * rowb);
-            T old[NCH];
-            if (even) {
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) old[ch] = cv[ch] ? dst[col[ch]] : T(0);
-            }
-            T y[NCH];
-            update_row<T, NCH>(Sb, rowb, i, rr, G, L, ovf, any_ovf, col, cv, y);
-#pragma unroll
-            for (int ch = 0; ch < NCH; ++ch) {
-                const T v = y[ch] * sigma;
-                if (cv[ch]) {
-                    dst[col[ch]] = v;
-                    es.nu2 += (double)v * (double)v;
-                    if (even) even_terms(es, v, old[ch]);
-                }
-            }
-        }
+        if (even)
+            lds_rows<true, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es);
+        else
+            lds_rows<false, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es);
         double tot;
         if (even)
             es = block_sum_even<NW>(es, red);
@@ -281,12 +291,122 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
     return out;
 }
 
-// Step a7 and the outputs: greedy matching by locally-dominant rounds on the
-// stored S (compute orientation), score in original row order, S_out, result.
+// Step a7, rows of at most kSortCols entries: the greedy order itself.  Each
+// stored row's columns are sorted once in that order (bitonic network, one
+// wave per row, 64 * E slots); then one wave repeats: the earliest entry among
+// every free row's first free column is matched, and rows whose column was
+// just taken move their pointer on past taken columns.  Each step is a wave
+// reduction instead of a workgroup round, which matters for nearly rank-one S,
+// where rounds of mutual bests match one pair each.  The sorted lists (16-bit
+// column indices) live in St; rptr in the lists' space, free by now.
+constexpr int kSortCols = 256;
+
+template <typename T, int E>
+__device__ __forceinline__ void sort_row(const T* Srow, int nC, uint16_t* ord) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    Rank<T> x[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int c = m * kWave + lane;
+        x[m] = c < nC ? Rank<T>::make(Srow[c], (uint32_t)c) : Rank<T>::none();
+    }
+    constexpr int N = kWave * E;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= kWave) {  // partner in the same lane
+                const int ms = stride / kWave;
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    if ((m & ms) == 0) {
+                        const bool up = ((m * kWave) & size) == 0;
+                        const Rank<T> a = x[m], b = x[m | ms];
+                        if (up ? (b < a) : (a < b)) {
+                            x[m] = b;
+                            x[m | ms] = a;
+                        }
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; ++m) {
+                    const int i = m * kWave + lane;
+                    const Rank<T> y = x[m].xor_lane(stride);
+                    const bool keep_min = ((i & stride) == 0) == ((i & size) == 0);
+                    if (keep_min ? (y < x[m]) : (x[m] < y)) x[m] = y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+        const int p = m * kWave + lane;
+        if (p < nC) ord[p] = (uint16_t)x[m].lo();
+    }
+}
+
+template <typename T, int NT, int E>
+__device__ __forceinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
+    constexpr int NW = NT / kWave;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = uni((int)threadIdx.x / kWave);
+    const int nR = sh.nR, nC = sh.nC;
+    const bool swp = sh.swap != 0;
+    uint16_t* ord = reinterpret_cast<uint16_t*>(St);
+    for (int r = wave; r < nR; r += NW) sort_row<T, E>(S + (long long)r * nC, nC, ord + (long long)r * nC);
+    __syncthreads();
+    if (wave == 0) {
+        int* rstate = G.rstate;
+        int* rbest = G.rbest;
+        int* cstate = G.cstate;
+        int* rptr = reinterpret_cast<int*>(G.rec);
+        for (int r = lane; r < nR; r += kWave) {
+            rstate[r] = -1;
+            rptr[r] = 0;
+            rbest[r] = ord[(long long)r * nC];
+        }
+        for (int c = lane; c < nC; c += kWave) cstate[c] = -1;
+        const int need = min(nR, nC);
+        for (int done = 0; done < need; ++done) {
+            Rank<T> best = Rank<T>::none();
+            for (int r = lane; r < nR; r += kWave) {
+                const int c = rbest[r];
+                if (rstate[r] == -1 && c >= 0) {
+                    const int key = swp ? c * nR + r : r * nC + c;
+                    const Rank<T> q = Rank<T>::make(S[(long long)r * nC + c], (uint32_t)key);
+                    if (q < best) best = q;
+                }
+            }
+            best = wave_min(best);
+            if (best.is_none()) break;
+            const int key = (int)best.lo();
+            const int r0 = swp ? key % nR : key / nC;
+            const int c0 = swp ? key / nR : key % nC;
+            if (lane == 0) {
+                rstate[r0] = c0;
+                cstate[c0] = r0;
+            }
+            // the wave's LDS accesses complete in order: the marks above are
+            // seen by the reads below
+            for (int r = lane; r < nR; r += kWave) {
+                if (rstate[r] == -1 && rbest[r] == c0) {
+                    const uint16_t* o = ord + (long long)r * nC;
+                    int q = rptr[r] + 1;
+                    while (q < nC && cstate[o[q]] != -1) ++q;
+                    rptr[r] = q;
+                    rbest[r] = q < nC ? (int)o[q] : -1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Step a7, longer rows: locally-dominant rounds, which for a strict total
+// order reach the same matching as the greedy order.
 template <typename T, int NT>
-__device__ __forceinline__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
-                                 const T* S, T* St, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
-                                 double* red, int* s_count) {
+__device__ __forceinline__ void greedy_rounds(const PairShape& sh, const T* S, T* St, const Lists<T>& G, int* s_count) {
     constexpr int NW = NT / kWave;
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -334,7 +454,7 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
             const T* line = is_row ? S + (long long)y0 * nC : St + (long long)y0 * nR;
             const int n = is_row ? nC : nR;
             const int* other = is_row ? cstate : rstate;
-            T bv = T(-1);
+            T bv = scan_start<T>();
             int bk = INT_MAX, bi = -1;
             for (int z0 = lane; z0 < n; z0 += 4 * kWave) {
                 T v[4];
@@ -391,9 +511,32 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
             }
         const int now = s_count[0];
         __syncthreads();
-        if (now == done) break;  // no progress: only possible with non-finite S
+        if (now == done) break;  // guard: the earliest free entry is always a mutual best
         done = now;
     }
+
+}
+
+// Step a7 and the outputs: greedy matching on the stored S (compute
+// orientation), score in original row order, S_out, result.
+template <typename T, int NT>
+__device__ __forceinline__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
+                                 const T* S, T* St, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
+                                 double* red, int* s_count) {
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x;
+    const int nC = sh.nC;
+    const bool swp = sh.swap != 0;
+    int* rstate = G.rstate;
+    int* cstate = G.cstate;
+    if (nC <= kWave)
+        greedy_sorted<T, NT, 1>(sh, S, St, G);
+    else if (nC <= 2 * kWave)
+        greedy_sorted<T, NT, 2>(sh, S, St, G);
+    else if (nC <= kSortCols)
+        greedy_sorted<T, NT, 4>(sh, S, St, G);
+    else
+        greedy_rounds<T, NT>(sh, S, St, G, s_count);
 
     const int nA = A.n, nB = B.n;
     const int64_t mo = (J.single || !J.match_off) ? 0 : J.match_off[p];
@@ -448,8 +591,8 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
             if (threadIdx.x == 0) write_invalid(res);
             return;
         }
-        const GraphRef R = sh.swap ? A : B;
-        const GraphRef C = sh.swap ? B : A;
+        const GraphRef R = pick_graph(sh.swap != 0, A, B);
+        const GraphRef C = pick_graph(sh.swap != 0, B, A);
         const int nR = sh.nR, nC = sh.nC;
         const size_t sbytes = align16((size_t)nR * nC * sizeof(T));
         const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
@@ -470,10 +613,9 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
     PairShape sh{};
     resolve_graphs(Jr, p, A, B, res);
     choose_shape(A.n, B.n, A.nnz, B.nnz, Jr.variant, (int)sizeof(T), &sh);
-    const GraphRef R = sh.swap ? A : B;
-    const GraphRef C = sh.swap ? B : A;
+    const int nnzR = sh.swap ? A.nnz : B.nnz, nnzC = sh.swap ? B.nnz : A.nnz;
     const size_t sbytes = align16((size_t)sh.nR * sh.nC * sizeof(T));
-    const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, sh.nR, sh.nC, R.nnz, C.nnz);
+    const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, sh.nR, sh.nC, nnzR, nnzC);
     const T* S = reinterpret_cast<const T*>(smem + (it.final_buf ? sbytes : 0));
     T* St = reinterpret_cast<T*>(smem + (it.final_buf ? 0 : sbytes));
     match_and_write<T, NT>(Jr, p, A, B, sh, S, St, G, it, res, red, s_count);
@@ -490,8 +632,8 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
         if (threadIdx.x == 0) write_invalid(res);
         return;
     }
-    const GraphRef R = sh.swap ? A : B;
-    const GraphRef C = sh.swap ? B : A;
+    const GraphRef R = pick_graph(sh.swap != 0, A, B);
+    const GraphRef C = pick_graph(sh.swap != 0, B, A);
     const int nR = sh.nR, nC = sh.nC;
     const Lists<T> G = carve_lists<T>(smem, nR, nC, R.nnz, C.nnz);
     T* slot = reinterpret_cast<T*>(J.gws) + (size_t)blockIdx.x * 2 * (size_t)J.slot_elems;

@@ -84,9 +84,68 @@ __device__ inline int wave_max(int x) {
     x = max(x, dpp<kDppMirror>(x));
     return max(max(lane_value(x, 0), lane_value(x, 16)), max(lane_value(x, 32), lane_value(x, 48)));
 }
+// Greedy order of S entries (Section 4.2's matching): value descending, ties by
+// the flat row-major index ascending; NaN entries (only from non-finite S)
+// come after every number, by index.  better(v, k, bv, bk): (v, k) is
+// strictly earlier than (bv, bk).  A scan starts from (NaN, INT_MAX), which
+// every entry beats.
 template <typename T>
 __device__ inline bool better(T v, int k, T bv, int bk) {
+    const bool vn = v != v, bn = bv != bv;
+    if (vn || bn) return vn == bn ? k < bk : bn;
     return v > bv || (v == bv && k < bk);
+}
+template <typename T>
+__device__ inline T scan_start() {
+    return T(__builtin_nan(""));
+}
+
+// The same order as one unsigned key per entry (smaller = earlier): the value
+// mapped to bits that grow as it falls (NaN largest, -0 as +0), then `lo`.
+__device__ inline uint32_t desc_bits(float v) {
+    if (v != v) return 0xFFFFFFFFu;
+    const uint32_t u = __float_as_uint(v == 0.0f ? 0.0f : v);
+    return (u & 0x80000000u) ? u : ~(u | 0x80000000u);
+}
+__device__ inline uint64_t desc_bits(double v) {
+    if (v != v) return ~0ull;
+    const uint64_t u = (uint64_t)__double_as_longlong(v == 0.0 ? 0.0 : v);
+    return (u & 0x8000000000000000ull) ? u : ~(u | 0x8000000000000000ull);
+}
+template <typename T>
+struct Rank;
+template <>
+struct Rank<float> {  // value bits and lo packed in one word
+    uint64_t k;
+    __device__ static Rank make(float v, uint32_t lo) { return Rank{((uint64_t)desc_bits(v) << 32) | lo}; }
+    __device__ static Rank none() { return Rank{~0ull}; }
+    __device__ bool operator<(const Rank& o) const { return k < o.k; }
+    __device__ bool is_none() const { return k == ~0ull; }
+    __device__ uint32_t lo() const { return (uint32_t)k; }
+    __device__ Rank xor_lane(int m) const { return Rank{(uint64_t)__shfl_xor((unsigned long long)k, m)}; }
+};
+template <>
+struct Rank<double> {
+    uint64_t hi;
+    uint32_t l;
+    __device__ static Rank make(double v, uint32_t lo) { return Rank{desc_bits(v), lo}; }
+    __device__ static Rank none() { return Rank{~0ull, ~0u}; }
+    __device__ bool operator<(const Rank& o) const { return hi < o.hi || (hi == o.hi && l < o.l); }
+    __device__ bool is_none() const { return hi == ~0ull && l == ~0u; }
+    __device__ uint32_t lo() const { return l; }
+    __device__ Rank xor_lane(int m) const {
+        return Rank{(uint64_t)__shfl_xor((unsigned long long)hi, m), (uint32_t)__shfl_xor((int)l, m)};
+    }
+};
+// Smallest rank over the wave, in every lane.
+template <typename T>
+__device__ inline Rank<T> wave_min(Rank<T> x) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        const Rank<T> y = x.xor_lane(m);
+        if (y < x) x = y;
+    }
+    return x;
 }
 template <int CTRL, typename T>
 __device__ inline void argmax_step(T& v, int& k, int& c) {
@@ -332,6 +391,21 @@ __device__ inline bool resolve_graphs(const PairJob& J, int p, GraphRef& A, Grap
     return A.n >= 1 && B.n >= 1;
 }
 
+// a if first, else b, field by field (a select of whole structs can leave
+// them in scratch memory).
+__device__ inline GraphRef pick_graph(bool first, const GraphRef& a, const GraphRef& b) {
+    GraphRef g;
+    g.n = first ? a.n : b.n;
+    g.nnz = first ? a.nnz : b.nnz;
+    g.rp = first ? a.rp : b.rp;
+    g.ci = first ? a.ci : b.ci;
+    g.w = first ? a.w : b.w;
+    g.cp = first ? a.cp : b.cp;
+    g.ri = first ? a.ri : b.ri;
+    g.eid = first ? a.eid : b.eid;
+    return g;
+}
+
 // Staged graph lists of one pair in LDS (layout of lds_lists_bytes).
 template <typename T>
 struct Lists {
@@ -376,7 +450,7 @@ __device__ inline Lists<T> carve_lists(unsigned char* base, int nR, int nC, int 
 // Stages the R rows (inline records) and both edge lists, writes S_0 into S,
 // and returns whether the pair is degenerate (a graph without positive weight).
 template <typename T, int NT>
-__device__ bool stage_pair(const GraphRef& R, const GraphRef& C, int nR, int nC, const Lists<T>& L, T* S, T s0) {
+__device__ __forceinline__ bool stage_pair(const GraphRef& R, const GraphRef& C, int nR, int nC, const Lists<T>& L, T* S, T s0) {
     const int tid = threadIdx.x;
     const int rowb = nC * (int)sizeof(T);
     static_assert(sizeof(RowRec<T>) == (sizeof(T) == 8 ? 80 : 48), "row record size");
@@ -472,18 +546,21 @@ template <typename T, int NCH>
 __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, const RowRec<T>& rr, const Lists<T>& G,
                                   const LaneList<T> (&L)[NCH], const uint64_t (&ovf)[NCH], bool any_ovf,
                                   const int (&col)[NCH], const bool (&cv)[NCH], T (&y)[NCH], int ch0 = 0) {
+    // Only the row's class drives control flow and is taken into SGPRs; its
+    // offsets and weights stay in VGPRs (a broadcast: every lane holds the same
+    // values), which saves a readfirstlane per field and row.
     const int ns = uni(rr.ns), np = uni(rr.np);
     int su[kDS], pu[kDP];
     T sw[kDS], pw[kDP];
 #pragma unroll
     for (int q = 0; q < kDS; ++q) {
-        su[q] = uni(rr.su[q]);
-        sw[q] = uni(rr.sw[q]);
+        su[q] = rr.su[q];
+        sw[q] = rr.sw[q];
     }
 #pragma unroll
     for (int q = 0; q < kDP; ++q) {
-        pu[q] = uni(rr.pu[q]);
-        pw[q] = uni(rr.pw[q]);
+        pu[q] = rr.pu[q];
+        pw[q] = rr.pw[q];
     }
     const bool fixed = ns <= kDS && np <= kDP;
     switch (fixed ? ns * 4 + np : -1) {
