@@ -301,104 +301,226 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
 // column indices) live in St; rptr in the lists' space, free by now.
 constexpr int kSortCols = 256;
 
-template <typename T, int E>
-__device__ __forceinline__ void sort_row(const T* Srow, int nC, uint16_t* ord) {
-    const int lane = (int)(threadIdx.x & (kWave - 1));
-    Rank<T> x[E];
+// One stage of the bitonic network over 64 * E slots (slot m * 64 + lane) of
+// RG independent rows, then the rest of the network; compile-time sizes keep
+// x[][] in registers.
+template <typename T, int E, int RG, int SIZE, int STRIDE>
+__device__ __forceinline__ void bitonic_from(Rank<T> (&x)[RG][E], int lane) {
+    if constexpr (SIZE <= kWave * E) {
+        if constexpr (STRIDE == 0) {
+            bitonic_from<T, E, RG, SIZE * 2, SIZE>(x, lane);
+        } else {
+            if constexpr (STRIDE >= kWave) {  // partner in the same lane
+                constexpr int MS = STRIDE / kWave;
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int c = m * kWave + lane;
-        x[m] = c < nC ? Rank<T>::make(Srow[c], (uint32_t)c) : Rank<T>::none();
-    }
-    constexpr int N = kWave * E;
+                for (int g = 0; g < RG; ++g)
 #pragma unroll
-    for (int size = 2; size <= N; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            if (stride >= kWave) {  // partner in the same lane
-                const int ms = stride / kWave;
-#pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    if ((m & ms) == 0) {
-                        const bool up = ((m * kWave) & size) == 0;
-                        const Rank<T> a = x[m], b = x[m | ms];
-                        if (up ? (b < a) : (a < b)) {
-                            x[m] = b;
-                            x[m | ms] = a;
+                    for (int m = 0; m < E; ++m) {
+                        if ((m & MS) == 0) {
+                            const bool up = ((m * kWave) & SIZE) == 0;
+                            const Rank<T> a = x[g][m], b = x[g][m | MS];
+                            if (up ? (b < a) : (a < b)) {
+                                x[g][m] = b;
+                                x[g][m | MS] = a;
+                            }
                         }
                     }
-                }
             } else {
+                Rank<T> y[RG][E];
 #pragma unroll
-                for (int m = 0; m < E; ++m) {
-                    const int i = m * kWave + lane;
-                    const Rank<T> y = x[m].xor_lane(stride);
-                    const bool keep_min = ((i & stride) == 0) == ((i & size) == 0);
-                    if (keep_min ? (y < x[m]) : (x[m] < y)) x[m] = y;
-                }
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int m = 0; m < E; ++m) y[g][m] = x[g][m].xor_lane(STRIDE);
+#pragma unroll
+                for (int g = 0; g < RG; ++g)
+#pragma unroll
+                    for (int m = 0; m < E; ++m) {
+                        const int i = m * kWave + lane;
+                        const bool keep_min = ((i & STRIDE) == 0) == ((i & SIZE) == 0);
+                        if (keep_min ? (y[g][m] < x[g][m]) : (x[g][m] < y[g][m])) x[g][m] = y[g][m];
+                    }
             }
+            bitonic_from<T, E, RG, SIZE, STRIDE / 2>(x, lane);
         }
-    }
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-        const int p = m * kWave + lane;
-        if (p < nC) ord[p] = (uint16_t)x[m].lo();
     }
 }
 
-template <typename T, int NT, int E>
-__device__ __forceinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
-    constexpr int NW = NT / kWave;
+// Sorts rows r0, r0 + step, ... (RG of them; those at or past nR are padding)
+// together: their networks are independent, so each stage's lane exchanges
+// for the RG rows are in flight at once.
+template <typename T, int E, int RG>
+__device__ __forceinline__ void sort_rows(const T* S, int nR, int nC, int r0, int step, uint16_t* ord) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
-    const int wave = uni((int)threadIdx.x / kWave);
+    Rank<T> x[RG][E];
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        const int r = r0 + g * step;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int c = m * kWave + lane;
+            x[g][m] = (r < nR && c < nC) ? Rank<T>::make(S[r * nC + c], (uint32_t)c) : Rank<T>::none();
+        }
+    }
+    bitonic_from<T, E, RG, 2, 1>(x, lane);
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+        const int r = r0 + g * step;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+            const int p = m * kWave + lane;
+            if (r < nR && p < nC) ord[r * nC + p] = (uint16_t)x[g][m].lo();
+        }
+    }
+}
+
+// Greedy walk over the sorted rows by one wave, rows r = lane + 64 m held in
+// registers (m < kWalkRows): each lane keeps its rows' current candidates, so
+// a step is a register minimum, one wave reduction and the pointer moves of
+// the rows that wanted the column just taken.
+constexpr int kWalkRows = 4;
+
+template <typename T>
+__device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, const uint16_t* ord, const Lists<T>& G) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
     const int nR = sh.nR, nC = sh.nC;
     const bool swp = sh.swap != 0;
+    int* rstate = G.rstate;
+    int* cstate = G.cstate;
+    auto key_of = [&](int r, int c) { return (uint32_t)(swp ? c * nR + r : r * nC + c); };
+    Rank<T> cr[kWalkRows];
+    int cc[kWalkRows], cp[kWalkRows];
+#pragma unroll
+    for (int m = 0; m < kWalkRows; ++m) {
+        const int r = m * kWave + lane;
+        cp[m] = 0;
+        cc[m] = -1;
+        cr[m] = Rank<T>::none();
+        if (r < nR) {
+            rstate[r] = -1;
+            cc[m] = ord[r * nC];
+            cr[m] = Rank<T>::make(S[r * nC + cc[m]], key_of(r, cc[m]));
+        }
+    }
+    for (int c = lane; c < nC; c += kWave) cstate[c] = -1;
+    const int need = min(nR, nC);
+    for (int done = 0; done < need; ++done) {
+        Rank<T> lb = cr[0];
+        int lm = 0;
+#pragma unroll
+        for (int m = 1; m < kWalkRows; ++m)
+            if (cr[m] < lb) {
+                lb = cr[m];
+                lm = m;
+            }
+        const Rank<T> gb = wave_min(lb);
+        if (gb.is_none()) break;
+        // ranks of real entries are distinct: exactly one lane holds the winner
+        const int wl = (int)__builtin_ctzll(__ballot(lb == gb));
+        int my_c = cc[0];
+#pragma unroll
+        for (int m = 1; m < kWalkRows; ++m)
+            if (lm == m) my_c = cc[m];
+        const int r0 = __builtin_amdgcn_readlane(lm * kWave + lane, wl);
+        const int c0 = __builtin_amdgcn_readlane(my_c, wl);
+        if (lane == wl) {
+#pragma unroll
+            for (int m = 0; m < kWalkRows; ++m)
+                if (lm == m) cr[m] = Rank<T>::none();
+        }
+        if (lane == 0) {
+            rstate[r0] = c0;
+            cstate[c0] = r0;
+        }
+        // Rows whose column was just taken move on to their next free column.
+        // The wave's LDS accesses complete in order: the marks above are seen
+        // by the reads below.
+#pragma unroll
+        for (int m = 0; m < kWalkRows; ++m) {
+            if (!cr[m].is_none() && cc[m] == c0) {
+                const int r = m * kWave + lane;
+                const uint16_t* o = ord + r * nC;
+                int q = cp[m] + 1;
+                while (q < nC && cstate[o[q]] != -1) ++q;
+                cp[m] = q;
+                if (q < nC) {
+                    cc[m] = o[q];
+                    cr[m] = Rank<T>::make(S[r * nC + cc[m]], key_of(r, cc[m]));
+                } else {
+                    cc[m] = -1;
+                    cr[m] = Rank<T>::none();
+                }
+            }
+        }
+    }
+}
+
+// The same walk with the rows' state in LDS (more than 64 * kWalkRows rows).
+template <typename T>
+__device__ __forceinline__ void greedy_walk_lds(const PairShape& sh, const T* S, const uint16_t* ord, const Lists<T>& G) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int nR = sh.nR, nC = sh.nC;
+    const bool swp = sh.swap != 0;
+    int* rstate = G.rstate;
+    int* rbest = G.rbest;
+    int* cstate = G.cstate;
+    int* rptr = reinterpret_cast<int*>(G.rec);
+    for (int r = lane; r < nR; r += kWave) {
+        rstate[r] = -1;
+        rptr[r] = 0;
+        rbest[r] = ord[r * nC];
+    }
+    for (int c = lane; c < nC; c += kWave) cstate[c] = -1;
+    const int need = min(nR, nC);
+    for (int done = 0; done < need; ++done) {
+        Rank<T> best = Rank<T>::none();
+        for (int r = lane; r < nR; r += kWave) {
+            const int c = rbest[r];
+            if (rstate[r] == -1 && c >= 0) {
+                const Rank<T> q = Rank<T>::make(S[r * nC + c], (uint32_t)(swp ? c * nR + r : r * nC + c));
+                if (q < best) best = q;
+            }
+        }
+        best = wave_min(best);
+        if (best.is_none()) break;
+        const int key = (int)best.lo();
+        const int r0 = swp ? key % nR : key / nC;
+        const int c0 = swp ? key / nR : key % nC;
+        if (lane == 0) {
+            rstate[r0] = c0;
+            cstate[c0] = r0;
+        }
+        for (int r = lane; r < nR; r += kWave) {
+            if (rstate[r] == -1 && rbest[r] == c0) {
+                const uint16_t* o = ord + r * nC;
+                int q = rptr[r] + 1;
+                while (q < nC && cstate[o[q]] != -1) ++q;
+                rptr[r] = q;
+                rbest[r] = q < nC ? (int)o[q] : -1;
+            }
+        }
+    }
+}
+
+template <typename T, int NT>
+__device__ __forceinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
+    constexpr int NW = NT / kWave;
+    const int wave = uni((int)threadIdx.x / kWave);
+    const int nR = sh.nR, nC = sh.nC;
     uint16_t* ord = reinterpret_cast<uint16_t*>(St);
-    for (int r = wave; r < nR; r += NW) sort_row<T, E>(S + (long long)r * nC, nC, ord + (long long)r * nC);
+    // rows sorted together by a wave: 4 short ones, 2 of 65-128 entries, 1 longer
+    if (nC <= kWave) {
+        for (int r = wave; r < nR; r += 4 * NW) sort_rows<T, 1, 4>(S, nR, nC, r, NW, ord);
+    } else if (nC <= 2 * kWave) {
+        for (int r = wave; r < nR; r += 2 * NW) sort_rows<T, 2, 2>(S, nR, nC, r, NW, ord);
+    } else {
+        for (int r = wave; r < nR; r += NW) sort_rows<T, 4, 1>(S, nR, nC, r, NW, ord);
+    }
     __syncthreads();
     if (wave == 0) {
-        int* rstate = G.rstate;
-        int* rbest = G.rbest;
-        int* cstate = G.cstate;
-        int* rptr = reinterpret_cast<int*>(G.rec);
-        for (int r = lane; r < nR; r += kWave) {
-            rstate[r] = -1;
-            rptr[r] = 0;
-            rbest[r] = ord[(long long)r * nC];
-        }
-        for (int c = lane; c < nC; c += kWave) cstate[c] = -1;
-        const int need = min(nR, nC);
-        for (int done = 0; done < need; ++done) {
-            Rank<T> best = Rank<T>::none();
-            for (int r = lane; r < nR; r += kWave) {
-                const int c = rbest[r];
-                if (rstate[r] == -1 && c >= 0) {
-                    const int key = swp ? c * nR + r : r * nC + c;
-                    const Rank<T> q = Rank<T>::make(S[(long long)r * nC + c], (uint32_t)key);
-                    if (q < best) best = q;
-                }
-            }
-            best = wave_min(best);
-            if (best.is_none()) break;
-            const int key = (int)best.lo();
-            const int r0 = swp ? key % nR : key / nC;
-            const int c0 = swp ? key / nR : key % nC;
-            if (lane == 0) {
-                rstate[r0] = c0;
-                cstate[c0] = r0;
-            }
-            // the wave's LDS accesses complete in order: the marks above are
-            // seen by the reads below
-            for (int r = lane; r < nR; r += kWave) {
-                if (rstate[r] == -1 && rbest[r] == c0) {
-                    const uint16_t* o = ord + (long long)r * nC;
-                    int q = rptr[r] + 1;
-                    while (q < nC && cstate[o[q]] != -1) ++q;
-                    rptr[r] = q;
-                    rbest[r] = q < nC ? (int)o[q] : -1;
-                }
-            }
-        }
+        if (nR <= kWalkRows * kWave)
+            greedy_walk<T>(sh, S, ord, G);
+        else
+            greedy_walk_lds<T>(sh, S, ord, G);
     }
     __syncthreads();
 }
@@ -529,12 +651,8 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
     const bool swp = sh.swap != 0;
     int* rstate = G.rstate;
     int* cstate = G.cstate;
-    if (nC <= kWave)
-        greedy_sorted<T, NT, 1>(sh, S, St, G);
-    else if (nC <= 2 * kWave)
-        greedy_sorted<T, NT, 2>(sh, S, St, G);
-    else if (nC <= kSortCols)
-        greedy_sorted<T, NT, 4>(sh, S, St, G);
+    if (nC <= kSortCols)
+        greedy_sorted<T, NT>(sh, S, St, G);
     else
         greedy_rounds<T, NT>(sh, S, St, G, s_count);
 

@@ -122,7 +122,19 @@ struct Rank<float> {  // value bits and lo packed in one word
     __device__ bool operator<(const Rank& o) const { return k < o.k; }
     __device__ bool is_none() const { return k == ~0ull; }
     __device__ uint32_t lo() const { return (uint32_t)k; }
+    __device__ bool operator==(const Rank& o) const { return k == o.k; }
     __device__ Rank xor_lane(int m) const { return Rank{(uint64_t)__shfl_xor((unsigned long long)k, m)}; }
+    template <int CTRL>
+    __device__ Rank dpp_move() const {
+        const uint32_t lo = (uint32_t)dpp<CTRL>((int)(uint32_t)k);
+        const uint32_t hi = (uint32_t)dpp<CTRL>((int)(uint32_t)(k >> 32));
+        return Rank{((uint64_t)hi << 32) | lo};
+    }
+    __device__ Rank read_lane(int ln) const {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, ln);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), ln);
+        return Rank{((uint64_t)hi << 32) | lo};
+    }
 };
 template <>
 struct Rank<double> {
@@ -133,19 +145,59 @@ struct Rank<double> {
     __device__ bool operator<(const Rank& o) const { return hi < o.hi || (hi == o.hi && l < o.l); }
     __device__ bool is_none() const { return hi == ~0ull && l == ~0u; }
     __device__ uint32_t lo() const { return l; }
+    __device__ bool operator==(const Rank& o) const { return hi == o.hi && l == o.l; }
     __device__ Rank xor_lane(int m) const {
         return Rank{(uint64_t)__shfl_xor((unsigned long long)hi, m), (uint32_t)__shfl_xor((int)l, m)};
     }
+    template <int CTRL>
+    __device__ Rank dpp_move() const {
+        const uint32_t h0 = (uint32_t)dpp<CTRL>((int)(uint32_t)hi);
+        const uint32_t h1 = (uint32_t)dpp<CTRL>((int)(uint32_t)(hi >> 32));
+        return Rank{((uint64_t)h1 << 32) | h0, (uint32_t)dpp<CTRL>((int)l)};
+    }
+    __device__ Rank read_lane(int ln) const {
+        const uint32_t h0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)hi, ln);
+        const uint32_t h1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(hi >> 32), ln);
+        return Rank{((uint64_t)h1 << 32) | h0, (uint32_t)__builtin_amdgcn_readlane((int)l, ln)};
+    }
 };
-// Smallest rank over the wave, in every lane.
+// Smallest rank over the wave (DPP steps inside the 16-lane rows, then the
+// four row results), in every lane; the whole wave must be active.
+template <int CTRL, typename T>
+__device__ inline void rank_min_step(Rank<T>& x) {
+    const Rank<T> y = x.template dpp_move<CTRL>();
+    if (y < x) x = y;
+}
+__device__ inline uint32_t wave_min_u32(uint32_t x) {
+    x = min(x, (uint32_t)dpp<kDppXor1>((int)x));
+    x = min(x, (uint32_t)dpp<kDppXor2>((int)x));
+    x = min(x, (uint32_t)dpp<kDppHalfMirror>((int)x));
+    x = min(x, (uint32_t)dpp<kDppMirror>((int)x));
+    const uint32_t a = min((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    const uint32_t b = min((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+    return min(a, b);
+}
+// FP32 ranks: the value word first, then the key among the lanes that hold
+// the smallest value word (two 32-bit reductions instead of one 64-bit one).
+__device__ inline Rank<float> wave_min(Rank<float> x) {
+    const uint32_t h = (uint32_t)(x.k >> 32);
+    const uint32_t hm = wave_min_u32(h);
+    const uint32_t lm = wave_min_u32(h == hm ? (uint32_t)x.k : 0xFFFFFFFFu);
+    return Rank<float>{((uint64_t)hm << 32) | lm};
+}
 template <typename T>
 __device__ inline Rank<T> wave_min(Rank<T> x) {
+    rank_min_step<kDppXor1>(x);
+    rank_min_step<kDppXor2>(x);
+    rank_min_step<kDppHalfMirror>(x);
+    rank_min_step<kDppMirror>(x);
+    Rank<T> b = x.read_lane(0);
 #pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) {
-        const Rank<T> y = x.xor_lane(m);
-        if (y < x) x = y;
+    for (int r = 16; r < kWave; r += 16) {
+        const Rank<T> y = x.read_lane(r);
+        if (y < b) b = y;
     }
-    return x;
+    return b;
 }
 template <int CTRL, typename T>
 __device__ inline void argmax_step(T& v, int& k, int& c) {
