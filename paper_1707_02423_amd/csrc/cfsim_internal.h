@@ -93,7 +93,7 @@ __host__ __device__ inline PairShape make_shape(int nA, int nB, int swap, int NW
 }
 
 // Bytes of one inline R-row record (see RowRec in pair.hip).
-__host__ __device__ inline size_t rowrec_bytes(int esize) { return esize == 8 ? 80 : 48; }
+__host__ __device__ inline size_t rowrec_bytes(int esize) { return esize == 8 ? 80 : 64; }
 
 // Bytes of the staged graph lists of one pair (both kernels keep them in LDS).
 // Layout: row records [nR] | row starts int2 [nR] | R succ, pred edges [nnzR]

@@ -12,7 +12,7 @@
 // The R side is wave-uniform: a row's record is broadcast from LDS to every
 // lane and the code is specialised on the row's (successor, predecessor)
 // counts, so every S read of a row is issued back to back.  The C side is per
-// lane: the lane's first 2 successors and 3 predecessors (padded with zero
+// lane: the lane's first 2 successors and 4 predecessors (padded with zero
 // weights) sit in VGPRs for the whole pair; longer lists add an overflow pass
 // reading the staged C lists.  Y goes to the second buffer un-normalised;
 // ||Y||^2 is reduced in FP64 in a fixed order and 1/||Y|| is folded into the

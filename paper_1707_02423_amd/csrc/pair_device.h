@@ -13,7 +13,7 @@ namespace cfsim {
 namespace dev {
 
 constexpr int kDS = 2;  // successors per lane column held in VGPRs
-constexpr int kDP = 3;  // predecessors per lane column held in VGPRs
+constexpr int kDP = 4;  // predecessors per lane column held in VGPRs
 
 template <typename T>
 struct alignas(sizeof(T) == 8 ? 16 : 8) Edge {
@@ -505,7 +505,7 @@ template <typename T, int NT>
 __device__ __forceinline__ bool stage_pair(const GraphRef& R, const GraphRef& C, int nR, int nC, const Lists<T>& L, T* S, T s0) {
     const int tid = threadIdx.x;
     const int rowb = nC * (int)sizeof(T);
-    static_assert(sizeof(RowRec<T>) == (sizeof(T) == 8 ? 80 : 48), "row record size");
+    static_assert(sizeof(RowRec<T>) == (sizeof(T) == 8 ? 80 : 64), "row record size");
     for (int r = tid; r < nR; r += NT) {
         const int sb = R.rp[r], se = R.rp[r + 1], pb = R.cp[r], pe = R.cp[r + 1];
         RowRec<T> x;
@@ -614,7 +614,7 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
         pu[q] = rr.pu[q];
         pw[q] = rr.pw[q];
     }
-    const bool fixed = ns <= kDS && np <= kDP;
+    const bool fixed = ns <= kDS && np <= 3;  // the specialised classes
     switch (fixed ? ns * 4 + np : -1) {
         case 0:
 #pragma unroll
