@@ -36,7 +36,6 @@ namespace cfsim {
 namespace {
 
 using dev::better;
-using dev::scan_start;
 using dev::uni;
 using dev::wave_argmax;
 using dev::wave_sum;
@@ -817,7 +816,8 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
             const int n = is_row ? nC : nR;
             const int* other = is_row ? cstate : rstate;
             const int kb = is_row ? x * nC : x, ks = is_row ? 1 : nC;
-            T bv = scan_start<T>();
+            T bv = T(-__builtin_inf());  // numbers first: NaN entries only if no number is left
+            bool nan_seen = false;
             int bk = INT_MAX, bi = -1;
             for (int y0 = lane; y0 < n; y0 += 8 * kWave) {
                 T v[8];
@@ -831,7 +831,9 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
                     const int y = y0 + u * kWave;
                     if (y < n && other[y] == -1) {
                         const int key = kb + y * ks;
-                        if (better(v[u], key, bv, bk)) {
+                        if (v[u] != v[u]) {
+                            nan_seen = true;
+                        } else if (v[u] > bv || (v[u] == bv && key < bk)) {
                             bv = v[u];
                             bk = key;
                             bi = y;
@@ -840,6 +842,21 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
                 }
             }
             wave_argmax(bv, bk, bi);
+            if (bi < 0 && __ballot(nan_seen) != 0) {
+                // no number left on the line: its free NaN entry with the smallest key
+                T z0v = T(-__builtin_inf());
+                int nk = INT_MAX, ni = -1;
+                for (int y = lane; y < n; y += kWave) {
+                    const int key = kb + y * ks;
+                    if (other[y] == -1 && line[y] != line[y] && key < nk) {
+                        nk = key;
+                        ni = y;
+                    }
+                }
+                if (ni >= 0) z0v = T(0);
+                wave_argmax(z0v, nk, ni);
+                bi = ni;
+            }
             if (lane == 0) {
                 if (is_row)
                     rbest[x] = bi;

@@ -576,7 +576,8 @@ __device__ __forceinline__ void greedy_rounds(const PairShape& sh, const T* S, T
             const T* line = is_row ? S + (long long)y0 * nC : St + (long long)y0 * nR;
             const int n = is_row ? nC : nR;
             const int* other = is_row ? cstate : rstate;
-            T bv = scan_start<T>();
+            T bv = T(-__builtin_inf());  // numbers first: NaN entries only if no number is left
+            bool nan_seen = false;
             int bk = INT_MAX, bi = -1;
             for (int z0 = lane; z0 < n; z0 += 4 * kWave) {
                 T v[4];
@@ -591,7 +592,9 @@ __device__ __forceinline__ void greedy_rounds(const PairShape& sh, const T* S, T
                     if (z < n && other[z] == -1) {
                         const int r = is_row ? y0 : z, c = is_row ? z : y0;
                         const int key = swp ? c * nR + r : r * nC + c;
-                        if (better(v[u], key, bv, bk)) {
+                        if (v[u] != v[u]) {
+                            nan_seen = true;
+                        } else if (v[u] > bv || (v[u] == bv && key < bk)) {
                             bv = v[u];
                             bk = key;
                             bi = z;
@@ -600,6 +603,22 @@ __device__ __forceinline__ void greedy_rounds(const PairShape& sh, const T* S, T
                 }
             }
             wave_argmax(bv, bk, bi);
+            if (bi < 0 && __ballot(nan_seen) != 0) {
+                // no number left on the line: its free NaN entry with the smallest key
+                T z0v = T(-__builtin_inf());
+                int nk = INT_MAX, ni = -1;
+                for (int z = lane; z < n; z += kWave) {
+                    const int r = is_row ? y0 : z, c = is_row ? z : y0;
+                    const int key = swp ? c * nR + r : r * nC + c;
+                    if (other[z] == -1 && line[z] != line[z] && key < nk) {
+                        nk = key;
+                        ni = z;
+                    }
+                }
+                if (ni >= 0) z0v = T(0);
+                wave_argmax(z0v, nk, ni);
+                bi = ni;
+            }
             if (lane == 0) {
                 if (is_row)
                     rbest[y0] = bi;

@@ -84,20 +84,15 @@ __device__ inline int wave_max(int x) {
     x = max(x, dpp<kDppMirror>(x));
     return max(max(lane_value(x, 0), lane_value(x, 16)), max(lane_value(x, 32), lane_value(x, 48)));
 }
-// Greedy order of S entries (Section 4.2's matching): value descending, ties by
+// Greedy order of S entries for the score's matching: value descending, ties by
 // the flat row-major index ascending; NaN entries (only from non-finite S)
 // come after every number, by index.  better(v, k, bv, bk): (v, k) is
-// strictly earlier than (bv, bk).  A scan starts from (NaN, INT_MAX), which
-// every entry beats.
+// strictly earlier than (bv, bk).
 template <typename T>
 __device__ inline bool better(T v, int k, T bv, int bk) {
     const bool vn = v != v, bn = bv != bv;
     if (vn || bn) return vn == bn ? k < bk : bn;
     return v > bv || (v == bv && k < bk);
-}
-template <typename T>
-__device__ inline T scan_start() {
-    return T(__builtin_nan(""));
 }
 
 // The same order as one unsigned key per entry (smaller = earlier): the value
