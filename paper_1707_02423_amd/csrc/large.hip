@@ -46,6 +46,7 @@ constexpr int kNWStep = kStepThreads / kWave;
 constexpr int kRowsPerWave = kTileRows / kNWStep;
 constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
 constexpr int kFinishThreads = 1024;
+constexpr int kCache = 8;  // cached partners per line in the matching
 constexpr int kLS = 2;                          // successors per lane column in registers
 constexpr int kLP = 3;                          // predecessors per lane column in registers
 constexpr int kSlotU = 0;                       // resize: U_k in slot k % 4
@@ -787,7 +788,19 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     // Greedy matching by locally dominant rounds: a free row and a free column
     // that are each other's best free partner are matched (the largest free
     // entry always is).  A stale best (-2) is recomputed by one wave scanning
-    // the row of S or the row of S^T: contiguous loads, eight per lane in flight.
+    // the row of S or the row of S^T (contiguous loads, eight per lane in
+    // flight).  The scan keeps each lane's two best free candidates and merges
+    // them into a prefix of the line's order (it stops where a lane's third
+    // candidate, unseen, could come next), cached in a free slot: when the
+    // line's best is taken, its next best free partner is the first cached one
+    // still free (partners are only ever taken, so nothing outside the prefix
+    // can rank before it), and the line is scanned again only when the cached
+    // ones are gone.  Near rank-one S makes every free line stale in every
+    // round; the cache saves most of those scans.  (Tiny pairs whose slot
+    // cannot hold the cache rescan every stale line.)
+    int* cache = (long long)(nR + nC) * kCache * (long long)sizeof(int) <= J.slot_elems * (long long)sizeof(T)
+                     ? reinterpret_cast<int*>(rz ? buf_of<T>(J, p, kSlotU + ((f + 2) & 3)) : buf_of<T>(J, p, (f + 2) & 3))
+                     : nullptr;
     int* rstate = reinterpret_cast<int*>(smem);
     int* rbest = rstate + nR;
     int* cstate = rbest + nR;
@@ -816,9 +829,10 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
             const int n = is_row ? nC : nR;
             const int* other = is_row ? cstate : rstate;
             const int kb = is_row ? x * nC : x, ks = is_row ? 1 : nC;
-            T bv = T(-__builtin_inf());  // numbers first: NaN entries only if no number is left
+            // numbers first: NaN entries only if no number is left
+            T v1 = T(-__builtin_inf()), v2 = T(-__builtin_inf());
+            int k1 = INT_MAX, k2 = INT_MAX, i1 = -1, i2 = -1;
             bool nan_seen = false;
-            int bk = INT_MAX, bi = -1;
             for (int y0 = lane; y0 < n; y0 += 8 * kWave) {
                 T v[8];
 #pragma unroll
@@ -833,16 +847,40 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
                         const int key = kb + y * ks;
                         if (v[u] != v[u]) {
                             nan_seen = true;
-                        } else if (v[u] > bv || (v[u] == bv && key < bk)) {
-                            bv = v[u];
-                            bk = key;
-                            bi = y;
+                        } else if (v[u] > v2 || (v[u] == v2 && key < k2)) {
+                            if (v[u] > v1 || (v[u] == v1 && key < k1)) {
+                                v2 = v1;
+                                k2 = k1;
+                                i2 = i1;
+                                v1 = v[u];
+                                k1 = key;
+                                i1 = y;
+                            } else {
+                                v2 = v[u];
+                                k2 = key;
+                                i2 = y;
+                            }
                         }
                     }
                 }
             }
-            wave_argmax(bv, bk, bi);
-            if (bi < 0 && __ballot(nan_seen) != 0) {
+            int* cl = cache ? cache + (long long)it * kCache : nullptr;
+            int head = 0, first = -1, got = 0;
+            for (int j = 0; j < kCache; ++j) {
+                if (__ballot(head == 2 && i2 >= 0) != 0) break;  // a lane's unseen third could be next
+                const T ov = head == 0 ? v1 : (head == 1 ? v2 : T(-__builtin_inf()));
+                const int ok = head == 0 ? k1 : (head == 1 ? k2 : INT_MAX);
+                const int oi = head == 0 ? i1 : (head == 1 ? i2 : -1);
+                T bv = ov;
+                int bk = ok, bi = oi;
+                wave_argmax(bv, bk, bi);
+                if (bi < 0) break;                   // no candidate left
+                if (oi == bi && ok == bk) ++head;   // keys are distinct: the one winning lane
+                if (cl && lane == 0) cl[j] = bi;
+                if (j == 0) first = bi;
+                got = j + 1;
+            }
+            if (first < 0 && __ballot(nan_seen) != 0) {
                 // no number left on the line: its free NaN entry with the smallest key
                 T z0v = T(-__builtin_inf());
                 int nk = INT_MAX, ni = -1;
@@ -855,13 +893,17 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
                 }
                 if (ni >= 0) z0v = T(0);
                 wave_argmax(z0v, nk, ni);
-                bi = ni;
+                first = ni;
+                if (cl && lane == 0) cl[0] = ni;
+                got = 1;
             }
+            if (cl && lane == 0)
+                for (int j = got; j < kCache; ++j) cl[j] = -1;
             if (lane == 0) {
                 if (is_row)
-                    rbest[x] = bi;
+                    rbest[x] = first;
                 else
-                    cbest[x] = bi;
+                    cbest[x] = first;
             }
         }
         __syncthreads();
@@ -876,10 +918,37 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
             }
         }
         __syncthreads();
+        // stale bests: the next cached free partner, else a new scan (-2)
         for (int r = tid; r < nR; r += kFinishThreads)
-            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) rbest[r] = -2;
+            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) {
+                int nb = -2;
+                if (cache) {
+                    const int* cl = cache + (long long)r * kCache;
+                    for (int q = 0; q < kCache; ++q) {
+                        const int y = cl[q];
+                        if (y >= 0 && cstate[y] == -1) {
+                            nb = y;
+                            break;
+                        }
+                    }
+                }
+                rbest[r] = nb;
+            }
         for (int c = tid; c < nC; c += kFinishThreads)
-            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) cbest[c] = -2;
+            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) {
+                int nb = -2;
+                if (cache) {
+                    const int* cl = cache + (long long)(nR + c) * kCache;
+                    for (int q = 0; q < kCache; ++q) {
+                        const int y = cl[q];
+                        if (y >= 0 && rstate[y] == -1) {
+                            nb = y;
+                            break;
+                        }
+                    }
+                }
+                cbest[c] = nb;
+            }
         const int now = s_count;
         __syncthreads();
         if (now == done) break;  // guard: the earliest free entry is always a mutual best
