@@ -610,7 +610,17 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
         pw[q] = rr.pw[q];
     }
     const bool fixed = ns <= kDS && np <= 3;  // the specialised classes
-    switch (fixed ? ns * 4 + np : -1) {
+    // the four common CFG rows first (tested on both counts so that the tests
+    // stay a chain, most frequent first), the rest through the switch
+    if (ns == 1 && np == 1) {
+        row_fixed<T, NCH, 1, 1>(Sb, su, sw, pu, pw, L, y);
+    } else if (ns == 2 && np == 1) {
+        row_fixed<T, NCH, 2, 1>(Sb, su, sw, pu, pw, L, y);
+    } else if (ns == 1 && np == 2) {
+        row_fixed<T, NCH, 1, 2>(Sb, su, sw, pu, pw, L, y);
+    } else if (ns == 2 && np == 2) {
+        row_fixed<T, NCH, 2, 2>(Sb, su, sw, pu, pw, L, y);
+    } else switch (fixed ? ns * 4 + np : -1) {
         case 0:
 #pragma unroll
             for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
@@ -619,12 +629,8 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
         case 2: row_fixed<T, NCH, 0, 2>(Sb, su, sw, pu, pw, L, y); break;
         case 3: row_fixed<T, NCH, 0, 3>(Sb, su, sw, pu, pw, L, y); break;
         case 4: row_fixed<T, NCH, 1, 0>(Sb, su, sw, pu, pw, L, y); break;
-        case 5: row_fixed<T, NCH, 1, 1>(Sb, su, sw, pu, pw, L, y); break;
-        case 6: row_fixed<T, NCH, 1, 2>(Sb, su, sw, pu, pw, L, y); break;
         case 7: row_fixed<T, NCH, 1, 3>(Sb, su, sw, pu, pw, L, y); break;
         case 8: row_fixed<T, NCH, 2, 0>(Sb, su, sw, pu, pw, L, y); break;
-        case 9: row_fixed<T, NCH, 2, 1>(Sb, su, sw, pu, pw, L, y); break;
-        case 10: row_fixed<T, NCH, 2, 2>(Sb, su, sw, pu, pw, L, y); break;
         case 11: row_fixed<T, NCH, 2, 3>(Sb, su, sw, pu, pw, L, y); break;
         default: {
             const int2 st = G.rstart[i];
