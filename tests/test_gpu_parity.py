@@ -87,6 +87,13 @@ def _plain_case(cf, ctx, graphs, a, b, dtype, max_iter=200, tol=1e-12):
     assert e <= gate, f"relative error {e:.3e}"
     assert got["iters"] == ref.iters and got["status"] == ref.status
     assert abs(got["nu"] - ref.nu) <= (1e-9 if dtype == "f64" else 1e-5) * max(1.0, ref.nu)
+    # the kernels take the even-step change from running sums (no stored S_{k-2});
+    # it must agree with the oracle's direct ||S_k - S_{k-2}||
+    if np.isfinite(ref.delta):
+        dtol = 1e-9 * ref.delta + 1e-14 if dtype == "f64" else 1e-5
+        assert abs(got["delta"] - ref.delta) <= dtol, (got["delta"], ref.delta)
+    else:
+        assert got["delta"] == float("inf")
     check_matching(got["S"], got["match"], ref.S)
     S64 = got["S"].astype(np.float64)
     assert abs(got["score"] - sum(S64[i, j] for i, j in enumerate(got["match"]) if j >= 0)) < 1e-12
