@@ -130,6 +130,19 @@ def test_plain_iteration_controls(cf, ctx, max_iter, tol):
         assert got["delta"] == float("inf")
 
 
+# The matching runs three ways: sorted rows walked in registers (at most 256
+# stored rows), the same walk with its state in LDS (more rows), and rounds of
+# mutual bests (stored rows over 256 entries).  Stored orientation: (60, 300)
+# keeps 300 rows of 60, (300, 250) stores 300 rows of 250, (600, 10) 10 rows
+# of 600 (global kernel).
+@pytest.mark.parametrize("nA,nB", [(60, 300), (300, 250), (600, 10)])
+def test_plain_matching_paths(cf, ctx, nA, nB):
+    rng = np.random.default_rng(nA + 17 * nB)
+    graphs = [make_cfg(nA, Grammar(counts="trip"), rng), make_cfg(nB, Grammar(counts="trip"), rng)]
+    got, ref = _plain_case(cf, ctx, graphs, 0, 1, "f64", max_iter=60)
+    own, _ = oracle.greedy_match(got["S"].astype(np.float64))
+    assert np.array_equal(got["match"], own)
+
 def test_plain_oscillating_pair_converges_on_even_step(cf, ctx):
     path = _g(3, [[0, 1, 1], [1, 2, 1]])
     loop = _g(1, [[0, 0, 1]])
