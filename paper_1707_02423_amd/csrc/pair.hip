@@ -99,12 +99,106 @@ __device__ __forceinline__ void even_terms(EvenSums& s, T y_new, T y_old) {
     s.dyy += dy * v;
 }
 
+// Rows of class CLS (order[b..e)) of one update, for the one-wave variant:
+// a class's rows share one straight-line body, no per-row dispatch.
+template <bool EVEN, typename T, int NCH, int CLS>
+__device__ __forceinline__ void class_rows(const int* order, int b, int e, const unsigned char* Sb, unsigned char* Nb,
+                                           int rowb, const Lists<T>& G, const LaneList<T> (&L)[NCH],
+                                           const uint64_t (&ovf)[NCH], bool any_ovf, const int (&col)[NCH],
+                                           const bool (&cv)[NCH], T sigma, EvenSums& es) {
+    for (int k = b; k < e; ++k) {
+        const int i = uni(order[k]);
+        const RowRec<T> rr = G.rec[i];
+        T* dst = reinterpret_cast<T*>(Nb + i * rowb);
+        T old[NCH];
+        if constexpr (EVEN) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) old[ch] = cv[ch] ? dst[col[ch]] : T(0);
+        }
+        T y[NCH];
+        update_row_class<T, NCH, CLS>(Sb, rowb, i, rr, G, L, ovf, any_ovf, col, cv, y);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const T v = y[ch] * sigma;
+            if (cv[ch]) {
+                dst[col[ch]] = v;
+                es.nu2 += (double)v * (double)v;
+                if constexpr (EVEN) even_terms(es, v, old[ch]);
+            }
+        }
+    }
+}
+
+// Rows in class order, stable (ascending row index within a class): order[0..nR)
+// and the class boundaries seg[0..kRowClasses], by the one wave of the
+// workgroup with two ballot passes.
+template <typename T>
+__device__ __forceinline__ void order_rows(const Lists<T>& G, int nR, int* order, int* seg) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    int cnt[kRowClasses];
+#pragma unroll
+    for (int c = 0; c < kRowClasses; ++c) cnt[c] = 0;
+    for (int base = 0; base < nR; base += kWave) {
+        const int r = base + lane;
+        const int cls = r < nR ? row_class(G.rec[r].ns, G.rec[r].np) : -1;
+#pragma unroll
+        for (int c = 0; c < kRowClasses; ++c) cnt[c] += __popcll(__ballot(cls == c));
+    }
+    int pos[kRowClasses];
+    int acc = 0;
+#pragma unroll
+    for (int c = 0; c < kRowClasses; ++c) {
+        pos[c] = acc;
+        if (lane == 0) seg[c] = acc;
+        acc += cnt[c];
+    }
+    if (lane == 0) seg[kRowClasses] = acc;
+    for (int base = 0; base < nR; base += kWave) {
+        const int r = base + lane;
+        const int cls = r < nR ? row_class(G.rec[r].ns, G.rec[r].np) : -1;
+#pragma unroll
+        for (int c = 0; c < kRowClasses; ++c) {
+            const uint64_t m = __ballot(cls == c);
+            if (cls == c) {
+                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+                order[pos[c] + below] = r;
+            }
+            pos[c] += __popcll(m);
+        }
+    }
+}
+
 // One update's rows of a wave: Y = (B S A^T + B^T S A) * sigma into Nb, with
 // nu^2 and, on even updates (EVEN), the even-step sums.
 template <bool EVEN, typename T, int NT, int NCH>
 __device__ __forceinline__ void lds_rows(const unsigned char* Sb, unsigned char* Nb, int rowb, int nR, const Lists<T>& G,
                                          const LaneList<T> (&L)[NCH], const uint64_t (&ovf)[NCH], bool any_ovf,
-                                         const int (&col)[NCH], const bool (&cv)[NCH], T sigma, EvenSums& es) {
+                                         const int (&col)[NCH], const bool (&cv)[NCH], T sigma, EvenSums& es,
+                                         const int* order, const int* seg) {
+    if constexpr (NT == kWave) {
+        // one wave: the rows class by class (for the larger variants the
+        // thirteen loop bodies cost more in registers and instruction cache
+        // than the dispatch they save)
+#define CFSIM_CLASS_ROWS(C)                                                                                       \
+    class_rows<EVEN, T, NCH, C>(order, uni(seg[C]), uni(seg[(C) + 1]), Sb, Nb, rowb, G, L, ovf, any_ovf, col, cv, \
+                                sigma, es)
+        CFSIM_CLASS_ROWS(0);
+        CFSIM_CLASS_ROWS(1);
+        CFSIM_CLASS_ROWS(2);
+        CFSIM_CLASS_ROWS(3);
+        CFSIM_CLASS_ROWS(4);
+        CFSIM_CLASS_ROWS(5);
+        CFSIM_CLASS_ROWS(6);
+        CFSIM_CLASS_ROWS(7);
+        CFSIM_CLASS_ROWS(8);
+        CFSIM_CLASS_ROWS(9);
+        CFSIM_CLASS_ROWS(10);
+        CFSIM_CLASS_ROWS(11);
+        CFSIM_CLASS_ROWS(12);
+#undef CFSIM_CLASS_ROWS
+        static_assert(kRowClasses == 13, "one call per row class");
+        return;
+    }
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
     for (int i = wave; i < nR; i += NW) {
@@ -135,7 +229,7 @@ __device__ __forceinline__ void lds_rows(const unsigned char* Sb, unsigned char*
 // holding the final S.
 template <typename T, int NT, int NCH>
 __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
-                               const Lists<T>& G, bool degenerate, double* red) {
+                               const Lists<T>& G, bool degenerate, double* red, const int* seg) {
     constexpr int NW = NT / kWave;
     const int nR = sh.nR, nC = sh.nC;
     const int esz = (int)sizeof(T);
@@ -166,9 +260,9 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
         const bool even = (k & 1) == 0;
         EvenSums es{0.0, 0.0, 0.0};
         if (even)
-            lds_rows<true, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es);
+            lds_rows<true, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es, G.rstate, seg);
         else
-            lds_rows<false, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es);
+            lds_rows<false, T, NT, NCH>(Sb, Nb, rowb, nR, G, L, ovf, any_ovf, col, cv, sigma, es, G.rstate, seg);
         double tot;
         if (even)
             es = block_sum_even<NW>(es, red);
@@ -716,7 +810,8 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
 }
 
 template <typename T, int NT, int NCHMAX>
-__device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+__device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count,
+                                         int* s_seg) {
     IterOut it;
     {
         GraphRef A{}, B{};
@@ -735,12 +830,13 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
         const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
         const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
         const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
+        if constexpr (NT == kWave) order_rows<T>(G, nR, G.rstate, s_seg);  // one wave: no barrier needed
         if (NCHMAX == 1 || sh.nchunk == 1)
-            it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red);
+            it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
         else if (NCHMAX == 2 || sh.nchunk == 2)
-            it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, red);
+            it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
         else
-            it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red);
+            it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
     }
     // The pair's graphs, shape and lists again, from fresh reads of the
     // arguments (the same values: the iteration does not change them).
@@ -785,13 +881,14 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
 // Persistent driver: one pair at a time per workgroup, pulled from the
 // bucket's queue (or the single pair of the plain path).
 template <bool GLOBAL, typename T, int NT, int NCH>
-__device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count) {
+__device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count,
+                                      int* s_seg) {
     if (J.single) {
         if (blockIdx.x == 0) {
             if constexpr (GLOBAL)
                 global_pair<T, NT>(J, 0, smem, red, s_count);
             else
-                lds_pair<T, NT, NCH>(J, 0, smem, red, s_count);
+                lds_pair<T, NT, NCH>(J, 0, smem, red, s_count, s_seg);
         }
         return;
     }
@@ -805,7 +902,7 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
         if constexpr (GLOBAL)
             global_pair<T, NT>(Jl, Jl.order[item], smem, red, s_count);
         else
-            lds_pair<T, NT, NCH>(Jl, Jl.order[item], smem, red, s_count);
+            lds_pair<T, NT, NCH>(Jl, Jl.order[item], smem, red, s_count, s_seg);
     }
 }
 
@@ -821,8 +918,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_si
 void pair_lds_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (NT / kWave)];
-    __shared__ int s_item, s_count[2];
-    drive<false, T, NT, NCH>(J, smem, red, &s_item, s_count);
+    __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
+    drive<false, T, NT, NCH>(J, smem, red, &s_item, s_count, s_seg);
 }
 
 template <typename T>
@@ -831,7 +928,7 @@ void pair_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
     __shared__ int s_item, s_count[2];
-    drive<true, T, kGlobalThreads, 1>(J, smem, red, &s_item, s_count);
+    drive<true, T, kGlobalThreads, 1>(J, smem, red, &s_item, s_count, nullptr);
 }
 
 // Pairs no kernel can take get an INVALID_INPUT result.

@@ -655,6 +655,56 @@ __device__ inline void update_row(const unsigned char* Sb, int rowb, int i, cons
     }
 }
 
+// Row classes: 12 specialised (successor, predecessor) counts (ns <= 2,
+// np <= 3) and one for every other row.
+constexpr int kRowClasses = 13;
+__device__ inline int row_class(int ns, int np) { return (ns <= kDS && np <= 3) ? ns * 4 + np : kRowClasses - 1; }
+
+// update_row for a row known to be in class CLS (no dispatch).
+template <typename T, int NCH, int CLS>
+__device__ __forceinline__ void update_row_class(const unsigned char* Sb, int rowb, int i, const RowRec<T>& rr,
+                                                 const Lists<T>& G, const LaneList<T> (&L)[NCH],
+                                                 const uint64_t (&ovf)[NCH], bool any_ovf, const int (&col)[NCH],
+                                                 const bool (&cv)[NCH], T (&y)[NCH]) {
+    int su[kDS], pu[kDP];
+    T sw[kDS], pw[kDP];
+#pragma unroll
+    for (int q = 0; q < kDS; ++q) {
+        su[q] = rr.su[q];
+        sw[q] = rr.sw[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kDP; ++q) {
+        pu[q] = rr.pu[q];
+        pw[q] = rr.pw[q];
+    }
+    if constexpr (CLS == 0) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) y[ch] = T(0);
+    } else if constexpr (CLS < kRowClasses - 1) {
+        row_fixed<T, NCH, CLS / 4, CLS % 4>(Sb, su, sw, pu, pw, L, y);
+    }
+    if constexpr (CLS < kRowClasses - 1) {
+        if (any_ovf) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ovf[ch]) y[ch] += row_extras<T>(Sb, ovf[ch], ch, G, CLS / 4, CLS % 4, su, sw, pu, pw);
+        }
+    } else {
+        const int ns = uni(rr.ns), np = uni(rr.np);
+        const int2 st = G.rstart[i];
+        const Edge<T>* se = G.sedge + uni(st.x);
+        const Edge<T>* pe = G.pedge + uni(st.y);
+        row_loop<T, NCH>(Sb, rowb, se, ns, pe, np, L, y);
+        if (any_ovf) {
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+                if (ovf[ch])
+                    y[ch] += row_overflow<T>(Sb, rowb, se, ns, pe, np, G.cinfo, G.csedge, G.cpedge, col[ch], cv[ch]);
+        }
+    }
+}
+
 // Lane lists of chunk ch; ovf = mask of the lanes whose lists are longer.
 template <typename T>
 __device__ inline void lane_setup(const Lists<T>& G, int ch, int nC, LaneList<T>& L, int& col, bool& cv,
