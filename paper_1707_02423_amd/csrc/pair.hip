@@ -468,12 +468,13 @@ __device__ __forceinline__ void sort_rows(const T* S, int nR, int nC, int r0, in
 }
 
 // Greedy walk over the sorted rows by one wave, rows r = lane + 64 m held in
-// registers (m < kWalkRows): each lane keeps its rows' current candidates, so
-// a step is a register minimum, one wave reduction and the pointer moves of
-// the rows that wanted the column just taken.
-constexpr int kWalkRows = 4;
+// registers (m < RM, instantiated for the row count): each lane keeps its
+// rows' current candidates, so a step is a register minimum, one wave
+// reduction and the pointer moves of the rows that wanted the column just
+// taken.
+constexpr int kWalkRows = 4;  // the most rows per lane held in registers
 
-template <typename T>
+template <typename T, int RM>
 __device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, const uint16_t* ord, const Lists<T>& G) {
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int nR = sh.nR, nC = sh.nC;
@@ -481,10 +482,10 @@ __device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, con
     int* rstate = G.rstate;
     int* cstate = G.cstate;
     auto key_of = [&](int r, int c) { return (uint32_t)(swp ? c * nR + r : r * nC + c); };
-    Rank<T> cr[kWalkRows];
-    int cc[kWalkRows], cp[kWalkRows];
+    Rank<T> cr[RM];
+    int cc[RM], cp[RM];
 #pragma unroll
-    for (int m = 0; m < kWalkRows; ++m) {
+    for (int m = 0; m < RM; ++m) {
         const int r = m * kWave + lane;
         cp[m] = 0;
         cc[m] = -1;
@@ -501,7 +502,7 @@ __device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, con
         Rank<T> lb = cr[0];
         int lm = 0;
 #pragma unroll
-        for (int m = 1; m < kWalkRows; ++m)
+        for (int m = 1; m < RM; ++m)
             if (cr[m] < lb) {
                 lb = cr[m];
                 lm = m;
@@ -512,13 +513,13 @@ __device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, con
         const int wl = (int)__builtin_ctzll(__ballot(lb == gb));
         int my_c = cc[0];
 #pragma unroll
-        for (int m = 1; m < kWalkRows; ++m)
+        for (int m = 1; m < RM; ++m)
             if (lm == m) my_c = cc[m];
         const int r0 = __builtin_amdgcn_readlane(lm * kWave + lane, wl);
         const int c0 = __builtin_amdgcn_readlane(my_c, wl);
         if (lane == wl) {
 #pragma unroll
-            for (int m = 0; m < kWalkRows; ++m)
+            for (int m = 0; m < RM; ++m)
                 if (lm == m) cr[m] = Rank<T>::none();
         }
         if (lane == 0) {
@@ -529,7 +530,7 @@ __device__ __forceinline__ void greedy_walk(const PairShape& sh, const T* S, con
         // The wave's LDS accesses complete in order: the marks above are seen
         // by the reads below.
 #pragma unroll
-        for (int m = 0; m < kWalkRows; ++m) {
+        for (int m = 0; m < RM; ++m) {
             if (!cr[m].is_none() && cc[m] == c0) {
                 const int r = m * kWave + lane;
                 const uint16_t* o = ord + r * nC;
@@ -611,8 +612,12 @@ __device__ __forceinline__ void greedy_sorted(const PairShape& sh, const T* S, T
     }
     __syncthreads();
     if (wave == 0) {
-        if (nR <= kWalkRows * kWave)
-            greedy_walk<T>(sh, S, ord, G);
+        if (nR <= kWave)
+            greedy_walk<T, 1>(sh, S, ord, G);
+        else if (nR <= 2 * kWave)
+            greedy_walk<T, 2>(sh, S, ord, G);
+        else if (nR <= kWalkRows * kWave)
+            greedy_walk<T, kWalkRows>(sh, S, ord, G);
         else
             greedy_walk_lds<T>(sh, S, ord, G);
     }
