@@ -596,8 +596,10 @@ __device__ __forceinline__ void greedy_walk_lds(const PairShape& sh, const T* S,
     }
 }
 
+// Kept out of line: runs once per pair, and inlined it constrains the
+// register allocation of the update loop in the same kernel.
 template <typename T, int NT>
-__device__ __forceinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
+__device__ __noinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
     const int nR = sh.nR, nC = sh.nC;
