@@ -3,10 +3,11 @@
  *
  * Method: Lim, Norris & Malony, "A Similarity Measure for GPU Kernel Subgraph
  * Matching" (arXiv 1707.02423).  Two control-flow graphs are compared through
- * their transition-probability matrices (Section 2, "Transition probability")
- * by the IsoRank solution of their Kronecker operator (Table 1, row "Iso";
- * Section 3.2), after an optional bilinear resize to a common size
- * (Section 3, Section 3.1).
+ * their transition-probability matrices (Section 3, Background, "Transition
+ * probability") by the IsoRank solution of their Kronecker operator (Table 1,
+ * row "Iso"; Section 4.2, Pairwise Comparison), after an optional bilinear
+ * resize to a common size (Section 4, Methodology; Section 4.1, Bilinear
+ * Interpolation).
  *
  * What every entry point computes, for a pair (A, B) with n_A and n_B nodes:
  *   S_0 = 1/sqrt(n_A n_B) (n_B x n_A, row i = node of B, column j = node of A)
@@ -14,6 +15,13 @@
  *   at even k: delta_k = ||S_k - S_{k-2}||_F; stop when delta_k < tol or
  *   k = max_iter; return S_k.  Greedy matching on S (value descending, then
  *   row-major flat index ascending), score = sum of matched entries.
+ *   margin = min over the greedy picks (i, j) of 1 - q / S_ij, q the largest
+ *   entry of row i or column j that was still free when (i, j) was picked
+ *   (+inf if no pick has such a rival; 0 for a pick below the smallest
+ *   normal number of the arithmetic type).  Every S here is non-negative,
+ *   so rounding errors are relative per entry: when every entry of another
+ *   S' differs from S by a relative amount below 0.5 * margin, S' has the
+ *   same greedy matching as S.
  *
  * Conventions for every entry point:
  *   - Pointers documented "device" must point to device memory (or memory
@@ -43,8 +51,8 @@ typedef enum {
     CFSIM_OK = 0,
     CFSIM_E_INVALID_ARG = -1,   /* NULL pointer, bad size, bad option value   */
     CFSIM_E_BAD_GRAPH = -2,     /* inconsistent graph description              */
-    CFSIM_E_NONFINITE = -3,     /* reserved for host-validated weights         */
-    CFSIM_E_NEGWEIGHT = -4,     /* reserved for host-validated weights         */
+    CFSIM_E_NONFINITE = -3,     /* a jump count is NaN or infinite (host check) */
+    CFSIM_E_NEGWEIGHT = -4,     /* a jump count is negative (host check)        */
     CFSIM_E_WORKSPACE = -5,     /* workspace smaller than the *_workspace_size */
     CFSIM_E_UNSUPPORTED = -6,   /* valid request this build does not serve     */
     CFSIM_E_HIP = -7            /* a HIP runtime call failed                   */
@@ -52,7 +60,7 @@ typedef enum {
 
 /* Arithmetic type of S. */
 enum { CFSIM_F64 = 0, CFSIM_F32 = 1 };
-/* Scale-to-common-size step (Section 3, Section 3.1). */
+/* Scale-to-common-size step (Section 4 and Section 4.1). */
 enum { CFSIM_RESIZE_NONE = 0, CFSIM_RESIZE_BILINEAR = 1 };
 
 /* Per-pair status bits (cfsim_pair_result.status). */
@@ -60,6 +68,19 @@ enum { CFSIM_RESIZE_NONE = 0, CFSIM_RESIZE_BILINEAR = 1 };
 #define CFSIM_HIT_MAX_ITER  2u  /* stopped at max_iter                         */
 #define CFSIM_DEGENERATE    4u  /* A or B has no positive weight: S = S_0      */
 #define CFSIM_INVALID_INPUT 8u  /* pair skipped (bad index or size over limit) */
+#define CFSIM_NEAR_TIE      16u /* margin <= tie_tol: the greedy matching may
+                                   change under perturbations of that size  */
+#define CFSIM_FP64_FINAL    32u /* an FP32 near-tie pair computed again in FP64
+                                   (CFSIM_FLAG_FP64_FINAL); its outputs are
+                                   the FP64 results                           */
+
+/* Option flags (cfsim_options.flags). */
+#define CFSIM_FLAG_FP64_FINAL 1u /* FP32 calls of cfsim_score / cfsim_score_batch
+                                    (no resize): every pair whose FP32 result is
+                                    CFSIM_NEAR_TIE is iterated again in FP64 on
+                                    the device, and its score, matching, S_out
+                                    (rounded to FP32), nu, delta, margin, iters
+                                    and status are replaced by the FP64 ones   */
 
 /* Pack error bits written by cfsim_pack into *err_flags. */
 #define CFSIM_PACK_BAD_INDEX 1  /* a jump endpoint outside [0, n_g): dropped   */
@@ -71,14 +92,19 @@ typedef struct {
     int32_t max_iter;   /* K_max >= 1: maximum number of updates                   */
     double tol;         /* stopping threshold on delta (>= 0; 0 = never converge)  */
     int32_t resize;     /* CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR              */
-    uint32_t flags;     /* must be 0                                               */
+    uint32_t flags;     /* 0 or CFSIM_FLAG_FP64_FINAL                              */
+    double tie_tol;     /* NEAR_TIE threshold on the relative greedy margin (>= 0,
+                           finite); 0 selects the default of the arithmetic type:
+                           1e-12 for FP64, 2e-5 for FP32 (twice the largest
+                           relative per-entry FP32 error measured at 200 updates) */
 } cfsim_options;
 
-/* Result of one pair (device memory, 32 bytes). */
+/* Result of one pair (device memory, 40 bytes). */
 typedef struct {
     double score;       /* sum of S over the greedy matching                       */
     double nu;          /* ||Y|| of the last update (tends to the spectral radius) */
     double delta;       /* last even-step ||S_k - S_{k-2}||_F (inf if none)        */
+    double margin;      /* relative greedy margin (see above; NaN if skipped)      */
     int32_t iters;      /* number of updates applied (0 if degenerate)             */
     uint32_t status;    /* CFSIM_* status bits                                     */
 } cfsim_pair_result;
@@ -135,7 +161,20 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device);
 void cfsim_context_destroy(cfsim_context* ctx);
 
 /*
- * Step a1 - transition probabilities (Section 2, "Transition probability"):
+ * Host validation of jump lists before a1 (all pointers are host memory):
+ * node_off[n_graphs+1], edge_off[n_graphs+1] (non-decreasing, starting at
+ * 0), src/dst/count[edge_off[n_graphs]].  Returns CFSIM_E_BAD_GRAPH for
+ * offsets that decrease or a graph with no node, or a jump endpoint outside
+ * [0, n_g); CFSIM_E_NONFINITE for a NaN or infinite count; CFSIM_E_NEGWEIGHT
+ * for a negative count (the first offending jump is named by
+ * cfsim_last_error()); CFSIM_OK otherwise.  Makes no HIP call.
+ */
+cfsim_status cfsim_check_jumps(int32_t n_graphs, const int64_t* node_off, const int64_t* edge_off,
+                               const int32_t* src, const int32_t* dst, const double* count);
+
+/*
+ * Step a1 - transition probabilities (Section 3, Background, "Transition
+ * probability"):
  * build a graph set from jump lists with execution counts.  For graph g the
  * jumps are src/dst/count[edge_off[g] .. edge_off[g+1]) with local node ids;
  * w = count / (sum of counts of the same source); a row with zero total
@@ -157,7 +196,7 @@ cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_node
  * row-major, opt->dtype; or n_M x n_M, n_M = max(n_A, n_B), when resized),
  * match_out[n_B] (or [n_M]) and res[1] are device memory; S_out and
  * match_out may be NULL.  With opt->resize = CFSIM_RESIZE_BILINEAR
- * (Section 3, Section 3.1: the smaller transition matrix X becomes
+ * (Section 4 and Section 4.1: the smaller transition matrix X becomes
  * R X R^T with the order-1 interpolation R from its m nodes to n_M points
  * at p (m - 1) / (n_M - 1)) the pair runs on the tiled path of
  * cfsim_score_large (a short launch sequence instead of one launch) and
@@ -192,8 +231,8 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set,
                                void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Step a9 - large pairs (Section 3.2 operator at hundreds to thousands of
- * nodes): same arguments, outputs and per-pair semantics as
+ * Step a9 - large pairs (the Table 1 "Iso" operator at hundreds to
+ * thousands of nodes): same arguments, outputs and per-pair semantics as
  * cfsim_score_batch, for pairs whose lists do not fit the batched kernels
  * (those report CFSIM_INVALID_INPUT there).  The iterates live in the
  * workspace (HBM); every update is one launch over the tiles of all pairs of

@@ -4,6 +4,7 @@ The compute path is libcfsim.so (HIP kernels for gfx950, C ABI in
 include/cfsim.h); `cfsim.py` is the thin ctypes binding.
 """
 from .cfsim import (  # noqa: F401
-    F32, F64, CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, NUM_BUCKETS, RESULT_DTYPE,
-    Batch, CfsimError, CfsimScore, Context, GraphSet, backward, bucket_kernel, lib, options, pack, score, score_batch, topk,
+    F32, F64, CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, NEAR_TIE, FP64_FINAL, NUM_BUCKETS, RESULT_DTYPE,
+    RESULT_BYTES, RESULT_STRIDE, Batch, CfsimError, CfsimScore, Context, GraphSet, backward, bucket_kernel,
+    check_jumps, lib, options, pack, score, score_batch, topk,
 )

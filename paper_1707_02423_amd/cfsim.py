@@ -19,14 +19,18 @@ LIB_PATH = os.path.join(_HERE, "libcfsim.so")
 
 F64, F32 = 0, 1
 RESIZE_NONE, RESIZE_BILINEAR = 0, 1
-CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT = 1, 2, 4, 8
+CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, NEAR_TIE, FP64_FINAL = 1, 2, 4, 8, 16, 32
+FLAG_FP64_FINAL = 1
 NUM_BUCKETS = 7  # batch buckets: 0-4 LDS kernels, 5 global-memory kernel, 6 invalid pairs
 PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
 
 STATUS_NAMES = {0: "CFSIM_OK", -1: "CFSIM_E_INVALID_ARG", -2: "CFSIM_E_BAD_GRAPH", -3: "CFSIM_E_NONFINITE",
                 -4: "CFSIM_E_NEGWEIGHT", -5: "CFSIM_E_WORKSPACE", -6: "CFSIM_E_UNSUPPORTED", -7: "CFSIM_E_HIP"}
 
-RESULT_DTYPE = np.dtype([("score", "<f8"), ("nu", "<f8"), ("delta", "<f8"), ("iters", "<i4"), ("status", "<u4")])
+RESULT_DTYPE = np.dtype([("score", "<f8"), ("nu", "<f8"), ("delta", "<f8"), ("margin", "<f8"), ("iters", "<i4"),
+                         ("status", "<u4")])
+RESULT_BYTES = RESULT_DTYPE.itemsize        # 40: sizeof(cfsim_pair_result)
+RESULT_STRIDE = RESULT_BYTES // 8           # doubles per result (score at 0)
 
 
 class CfsimError(RuntimeError):
@@ -37,7 +41,7 @@ class CfsimError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("resize", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+                ("resize", ctypes.c_int32), ("flags", ctypes.c_uint32), ("tie_tol", ctypes.c_double)]
 
 
 class Graph(ctypes.Structure):
@@ -65,6 +69,7 @@ SIGNATURES = {
     "cfsim_version": (ctypes.c_char_p, []),
     "cfsim_context_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int]),
     "cfsim_context_destroy": (None, [_P]),
+    "cfsim_check_jumps": (ctypes.c_int, [_I32, _P, _P, _P, _P, _P]),
     "cfsim_pack_workspace_size": (_SZ, [_I32, _I64, _I64]),
     "cfsim_pack": (ctypes.c_int, [_P, _I32, _I64, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _SZ,
                                   _P]),
@@ -121,10 +126,11 @@ def _stream(stream) -> int | None:
     return stream.cuda_stream or None
 
 
-def options(dtype="f64", max_iter=200, tol=1e-12, resize="none") -> Options:
+def options(dtype="f64", max_iter=200, tol=1e-12, resize="none", tie_tol=0.0, fp64_final=False) -> Options:
     d = {"f64": F64, "f32": F32}[dtype] if isinstance(dtype, str) else int(dtype)
     r = {"none": RESIZE_NONE, "bilinear": RESIZE_BILINEAR}[resize] if isinstance(resize, str) else int(resize)
-    return Options(dtype=d, max_iter=int(max_iter), tol=float(tol), resize=r, flags=0)
+    return Options(dtype=d, max_iter=int(max_iter), tol=float(tol), resize=r,
+                   flags=FLAG_FP64_FINAL if fp64_final else 0, tie_tol=float(tie_tol))
 
 
 class Context:
@@ -221,9 +227,23 @@ def concat_coo(graphs):
     return node_off, edge_off, src, dst, cnt
 
 
+def check_jumps(graphs):
+    """Host validation of jump lists (cfsim_check_jumps): raises CfsimError
+    (E_BAD_GRAPH, E_NONFINITE, E_NEGWEIGHT) naming the first bad jump."""
+    node_off, edge_off, src, dst, cnt = concat_coo(graphs)
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    cnt = np.ascontiguousarray(cnt, np.float64)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().cfsim_check_jumps(len(graphs), p(node_off), p(edge_off), p(src), p(dst), p(cnt)))
+
+
 def pack(ctx: Context, graphs, device=None, stream=None, check=True) -> GraphSet:
-    """Step a1 on the device: jump lists with counts -> CSR/CSC transition matrices."""
+    """Step a1 on the device: jump lists with counts -> CSR/CSC transition matrices.
+    With check=True the lists are validated on the host first (check_jumps)."""
     dev = torch.device("cuda", ctx.device) if device is None else torch.device(device)
+    if check and graphs:
+        check_jumps(graphs)
     node_off, edge_off, src, dst, cnt = concat_coo(graphs)
     G = len(graphs)
     N, E = int(node_off[-1]), int(edge_off[-1])
@@ -256,9 +276,9 @@ def _torch_dtype(opt: Options):
 
 
 def score(ctx: Context, gs: GraphSet, a: int, b: int, dtype="f64", max_iter=200, tol=1e-12, resize="none",
-          want_S=True, stream=None, sync=True):
+          want_S=True, stream=None, sync=True, tie_tol=0.0, fp64_final=False):
     """Plain path, one pair: A = graph a, B = graph b of the set."""
-    opt = options(dtype, max_iter, tol, resize)
+    opt = options(dtype, max_iter, tol, resize, tie_tol, fp64_final)
     A, B = gs.graph(a), gs.graph(b)
     dev = gs.w.device
     nA, nB = A.n, B.n
@@ -266,7 +286,7 @@ def score(ctx: Context, gs: GraphSet, a: int, b: int, dtype="f64", max_iter=200,
         nA = nB = max(A.n, B.n)
     S = torch.empty(nB * nA, dtype=_torch_dtype(opt), device=dev) if want_S else None
     match = torch.empty(nB, dtype=torch.int32, device=dev)
-    res = torch.empty(32, dtype=torch.uint8, device=dev)
+    res = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=dev)
     ws_bytes = lib().cfsim_score_workspace_size(ctx.handle, A.n, B.n, ctypes.byref(opt))
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
     _check(lib().cfsim_score(ctx.handle, ctypes.byref(A), ctypes.byref(B), ctypes.byref(opt), _ptr(S), _ptr(match),
@@ -294,19 +314,20 @@ class Batch:
     """
 
     def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
-                 resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch"):
+                 resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch",
+                 tie_tol=0.0, fp64_final=False):
         if path not in ("batch", "large"):
             raise ValueError("path must be 'batch' (cfsim_score_batch) or 'large' (cfsim_score_large)")
         self.path = path
         self.ctx, self.gs = ctx, gs
-        self.opt = options(dtype, max_iter, tol, resize)
+        self.opt = options(dtype, max_iter, tol, resize, tie_tol, fp64_final)
         dev = gs.w.device
         self.pair_a_h = np.asarray(pair_a, np.int32)
         self.pair_b_h = np.asarray(pair_b, np.int32)
         self.n_pairs = int(self.pair_a_h.shape[0])
         self.pair_a = torch.as_tensor(self.pair_a_h).to(dev)
         self.pair_b = torch.as_tensor(self.pair_b_h).to(dev)
-        self.res = torch.empty(max(self.n_pairs, 1) * 32, dtype=torch.uint8, device=dev)
+        self.res = torch.empty(max(self.n_pairs, 1) * RESULT_BYTES, dtype=torch.uint8, device=dev)
         sizes = gs.sizes().astype(np.int64)
 
         def size_of(idx):  # 0 for ids outside the set (the kernel marks those pairs invalid)
@@ -351,11 +372,11 @@ class Batch:
 
     def topk(self, k: int, stream=None):
         """Top-k of this batch's scores, on the device (call after run())."""
-        scores = self.res[: self.n_pairs * 32].view(torch.float64)
-        return topk(self.ctx, scores, k, stride=4, n=self.n_pairs, stream=stream)
+        scores = self.res[: self.n_pairs * RESULT_BYTES].view(torch.float64)
+        return topk(self.ctx, scores, k, stride=RESULT_STRIDE, n=self.n_pairs, stream=stream)
 
     def results(self) -> np.ndarray:
-        return self.res[: self.n_pairs * 32].cpu().numpy().view(RESULT_DTYPE)
+        return self.res[: self.n_pairs * RESULT_BYTES].cpu().numpy().view(RESULT_DTYPE)
 
     def matches(self):
         m = self.match.cpu().numpy()
@@ -375,7 +396,7 @@ def bucket_kernel(bucket: int, dtype="f32") -> str:
 def topk(ctx: Context, scores: torch.Tensor, k: int, stride: int = 1, n: int | None = None, stream=None):
     """Step a11 on the device: indices and values of the k best scores
     (ties to the lower index, NaN ranks last).  `scores` is a float64 device
-    tensor read with `stride` (4 reads the score field of a result array)."""
+    tensor read with `stride` (RESULT_STRIDE reads the score field of a result array)."""
     n = int(scores.numel() // stride) if n is None else int(n)
     dev = scores.device
     idx = torch.empty(k, dtype=torch.int32, device=dev)
@@ -424,7 +445,7 @@ class CfsimScore(torch.autograd.Function):
         ctx_.batch = b
         ctx_.w = w
         ctx_.checkpoint_every = checkpoint_every
-        return b.res[: b.n_pairs * 32].view(torch.float64)[0::4].clone()
+        return b.res[: b.n_pairs * RESULT_BYTES].view(torch.float64)[0::RESULT_STRIDE].clone()
 
     @staticmethod
     def backward(ctx_, grad_scores):
@@ -434,9 +455,10 @@ class CfsimScore(torch.autograd.Function):
 
 
 def score_batch(ctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, resize="none", want_match=True,
-                want_S=False, path="batch"):
+                want_S=False, path="batch", tie_tol=0.0, fp64_final=False):
     """Batched (or large-pair) path: run once, synchronise, return (results, matches, S list)."""
-    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S, path=path)
+    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S, path=path,
+              tie_tol=tie_tol, fp64_final=fp64_final)
     b.run()
     torch.cuda.synchronize()
     return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)

@@ -62,7 +62,29 @@ cfsim_status check_options(const cfsim_options* o) {
         return fail(CFSIM_E_INVALID_ARG, "tol must be finite and >= 0");
     if (o->resize != CFSIM_RESIZE_NONE && o->resize != CFSIM_RESIZE_BILINEAR)
         return fail(CFSIM_E_INVALID_ARG, "resize must be CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR");
-    if (o->flags != 0) return fail(CFSIM_E_INVALID_ARG, "flags must be 0");
+    if ((o->flags & ~CFSIM_FLAG_FP64_FINAL) != 0)
+        return fail(CFSIM_E_INVALID_ARG, "flags: unknown bits %#x", o->flags & ~CFSIM_FLAG_FP64_FINAL);
+    if ((o->flags & CFSIM_FLAG_FP64_FINAL) && o->dtype != CFSIM_F32)
+        return fail(CFSIM_E_INVALID_ARG, "CFSIM_FLAG_FP64_FINAL applies to FP32 calls only");
+    if (!(o->tie_tol >= 0.0) || !std::isfinite(o->tie_tol))
+        return fail(CFSIM_E_INVALID_ARG, "tie_tol must be finite and >= 0");
+    return CFSIM_OK;
+}
+
+// NEAR_TIE threshold of a call in arithmetic type `dtype`: the option, or
+// the type's default (twice the largest relative per-entry error against
+// FP64 measured on the all-pairs workload for FP32; the C9-style floor for
+// FP64).
+double tie_tol_of(const cfsim_options* o, int dtype) {
+    if (o->tie_tol > 0.0 && dtype == o->dtype) return o->tie_tol;
+    return dtype == CFSIM_F64 ? 1e-12 : 2e-5;
+}
+
+bool fp64_final(const cfsim_options* o) { return (o->flags & CFSIM_FLAG_FP64_FINAL) != 0; }
+
+// The tiled path (large pairs, resize) has no FP64 pass.
+cfsim_status check_no_fp64_final(const cfsim_options* o) {
+    if (fp64_final(o)) return fail(CFSIM_E_UNSUPPORTED, "CFSIM_FLAG_FP64_FINAL on the tiled path (large pairs, resize)");
     return CFSIM_OK;
 }
 
@@ -149,6 +171,7 @@ size_t slot_bytes(const cfsim_context* ctx, int v, int esize, int max_nodes) {
     if (v == cfsim::kBucketGlobal) return align256(wgs * 2 * (size_t)global_slot_elems(max_nodes) * esize);
     return 0;
 }
+// esize: the largest arithmetic type of the call (8 with the FP64 pass).
 size_t batch_ws_bytes(const cfsim_context* ctx, int64_t n_pairs, int esize, int max_nodes) {
     size_t b = align256((size_t)n_pairs * 4) + align256(2 * cfsim::kBuckets * 4) + align256(cfsim::kBuckets * 4);
     for (int v = 0; v <= cfsim::kBucketGlobal; ++v) b += slot_bytes(ctx, v, esize, max_nodes);
@@ -198,6 +221,7 @@ cfsim::LargeJob large_job(const cfsim_options* opt, int64_t n_pairs, int max_nod
     J.max_nodes = max_nodes;
     J.max_iter = opt->max_iter;
     J.tol = opt->tol;
+    J.tie_tol = tie_tol_of(opt, opt->dtype);
     J.resize = opt->resize == CFSIM_RESIZE_BILINEAR;
     J.res = res;
     J.match = match;
@@ -357,6 +381,36 @@ void cfsim_context_destroy(cfsim_context* ctx) {
     delete ctx;
 }
 
+// ------------------------------------------------------------------ host check of jump lists
+cfsim_status cfsim_check_jumps(int32_t n_graphs, const int64_t* node_off, const int64_t* edge_off,
+                               const int32_t* src, const int32_t* dst, const double* count) {
+    if (n_graphs < 0) return fail(CFSIM_E_INVALID_ARG, "n_graphs must be >= 0");
+    if (!node_off || !edge_off) return fail(CFSIM_E_INVALID_ARG, "node_off or edge_off is NULL");
+    if (node_off[0] != 0 || edge_off[0] != 0) return fail(CFSIM_E_BAD_GRAPH, "node_off[0] and edge_off[0] must be 0");
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        if (node_off[g + 1] <= node_off[g])
+            return fail(CFSIM_E_BAD_GRAPH, "graph %d: node_off must increase (every graph has a node)", g);
+        if (edge_off[g + 1] < edge_off[g]) return fail(CFSIM_E_BAD_GRAPH, "graph %d: edge_off decreases", g);
+    }
+    if (edge_off[n_graphs] > 0 && (!src || !dst || !count))
+        return fail(CFSIM_E_INVALID_ARG, "src, dst or count is NULL");
+    for (int32_t g = 0; g < n_graphs; ++g) {
+        const int64_t n = node_off[g + 1] - node_off[g];
+        for (int64_t t = edge_off[g]; t < edge_off[g + 1]; ++t) {
+            if (src[t] < 0 || src[t] >= n || dst[t] < 0 || dst[t] >= n)
+                return fail(CFSIM_E_BAD_GRAPH, "graph %d, jump %lld: endpoint (%d, %d) outside [0, %lld)", g,
+                            (long long)(t - edge_off[g]), src[t], dst[t], (long long)n);
+            if (!std::isfinite(count[t]))
+                return fail(CFSIM_E_NONFINITE, "graph %d, jump %lld: count is not finite", g,
+                            (long long)(t - edge_off[g]));
+            if (count[t] < 0.0)
+                return fail(CFSIM_E_NEGWEIGHT, "graph %d, jump %lld: negative count %g", g,
+                            (long long)(t - edge_off[g]), count[t]);
+        }
+    }
+    return ok();
+}
+
 // ------------------------------------------------------------------ pack (a1)
 size_t cfsim_pack_workspace_size(int32_t n_graphs, int64_t total_nodes, int64_t total_edges) {
     (void)n_graphs;
@@ -420,7 +474,7 @@ static int plain_variant(int nA, int nB, int nnzA, int nnzB, int esize, cfsim::P
 size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b, const cfsim_options* opt) {
     (void)ctx;
     if (n_a < 1 || n_b < 1 || !opt) return 0;
-    const size_t esize = esize_of(opt->dtype);
+    const size_t esize = fp64_final(opt) ? 8 : esize_of(opt->dtype);
     if (opt->resize == CFSIM_RESIZE_BILINEAR) return large_ws_bytes(1, n_a > n_b ? n_a : n_b, (int)esize, 6);
     // the two iterate buffers of the global kernel (the LDS kernels need none)
     return align256(2 * (size_t)n_a * (size_t)n_b * esize);
@@ -438,6 +492,7 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     if (opt->resize == CFSIM_RESIZE_BILINEAR) {
         // scaled pairs run on the tiled path (the resized operator in factored form)
         const int M = A->n > B->n ? A->n : B->n;
+        if ((s = check_no_fp64_final(opt)) != CFSIM_OK) return s;
         if ((s = check_large_limits(M, opt)) != CFSIM_OK) return s;
         const size_t need = cfsim_score_workspace_size(ctx, A->n, B->n, opt);
         if (ws_bytes < need || !ws)
@@ -461,12 +516,19 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     const size_t need = cfsim_score_workspace_size(ctx, A->n, B->n, opt);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    // FP64 pass (near-tie FP32 result): the first FP64 kernel that holds the pair
+    int variant64 = -1;
+    if (fp64_final(opt)) {
+        cfsim::PairShape sh64;
+        variant64 = plain_variant(A->n, B->n, A->nnz, B->nnz, 8, &sh64);
+    }
     cfsim::PairJob job{};
     job.single = 1;
     job.ga = ref_of(A);
     job.gb = ref_of(B);
     job.max_iter = opt->max_iter;
     job.tol = opt->tol;
+    job.tie_tol = tie_tol_of(opt, opt->dtype);
     job.res = res;
     job.match = match_out;
     job.S_out = S_out;
@@ -475,8 +537,16 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     job.slot_elems = (long long)A->n * B->n;
     int e = (int)hipSetDevice(ctx->device);
     if (e != 0) return hip_fail(e, "hipSetDevice");
-    e = cfsim::launch_pair_lds(variant, opt->dtype, job, 1, static_cast<hipStream_t>(stream));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    e = cfsim::launch_pair_lds(variant, opt->dtype, job, 1, st);
     if (e != 0) return hip_fail(e, "pair kernel launch");
+    if (variant64 >= 0) {  // runs only if the FP32 result is a near tie (decided on the device)
+        job.refine = 1;
+        job.variant = variant64;
+        job.tie_tol = tie_tol_of(opt, CFSIM_F64);
+        e = cfsim::launch_pair_lds(variant64, CFSIM_F64, job, 1, st);
+        if (e != 0) return hip_fail(e, "FP64 pass launch");
+    }
     return ok();
 }
 
@@ -488,20 +558,23 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
         if (set->max_nodes > cfsim::kLargeMaxNodes) return 0;
         return large_ws_bytes(n_pairs > 0 ? n_pairs : 1, set->max_nodes, esize_of(opt->dtype), 6);
     }
-    return batch_ws_bytes(ctx, n_pairs, esize_of(opt->dtype), set->max_nodes);
+    return batch_ws_bytes(ctx, n_pairs, fp64_final(opt) ? 8 : esize_of(opt->dtype), set->max_nodes);
 }
 
-static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
-                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
-                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
-                         hipStream_t st, bool timed) {
-    const int esize = esize_of(opt->dtype);
-    const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
-    cfsim::PlanJob plan;
+// Plan and bucket kernels of one pass of the batched path on `st`: dtype is
+// the pass's arithmetic type; filter (the FP32 results) restricts the FP64
+// pass of an FP32 call to its near-tie pairs.
+static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a, const int32_t* pair_b,
+                        int64_t n_pairs, const cfsim_options* opt, int dtype, const cfsim_pair_result* filter,
+                        cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                        const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed) {
+    const int esize = esize_of(dtype);
+    cfsim::PlanJob plan{};
     plan.set = ref_of(set);
     plan.pair_a = pair_a;
     plan.pair_b = pair_b;
     plan.n_pairs = n_pairs;
+    plan.filter = filter;
     plan.esize = esize;
     plan.slot_elems = global_slot_elems(set->max_nodes);
     plan.order = b.order;
@@ -517,16 +590,19 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
     job.order = b.order;
     job.max_iter = opt->max_iter;
     job.tol = opt->tol;
+    job.tie_tol = tie_tol_of(opt, dtype);
+    job.refine = filter != nullptr;
     job.res = res;
     job.match = match;
     job.match_off = match_off;
     job.S_out = S_out;
     job.S_off = S_off;
-    const int d = dtype_index(opt->dtype);
+    const int d = dtype_index(dtype);
     // The bucket kernels run one after another on the caller's stream, each
     // with the whole device: a bucket's persistent grid drains its queue
     // longest pair first, so its tail is about one pair long.
     for (int v = 0; v < cfsim::kBuckets; ++v) {
+        if (filter && v == cfsim::kBucketInvalid) continue;  // the FP64 pass leaves no pair invalid
         job.bounds = b.bounds + 2 * v;
         job.queue = b.queues + v;
         job.variant = v;
@@ -541,10 +617,26 @@ static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const i
             grid = ctx->grid[d][v];
         }
         if (timed && (e = (int)hipEventRecord(ctx->t0[v], st)) != 0) return e;
-        if ((e = cfsim::launch_pair_lds(v, opt->dtype, job, grid, st)) != 0) return e;
+        if ((e = cfsim::launch_pair_lds(v, dtype, job, grid, st)) != 0) return e;
         if (timed && (e = (int)hipEventRecord(ctx->t1[v], st)) != 0) return e;
     }
+    (void)esize;
     return 0;
+}
+
+static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                         const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                         int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                         hipStream_t st, bool timed) {
+    const int esize = fp64_final(opt) ? 8 : esize_of(opt->dtype);
+    const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
+    int e = enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, opt->dtype, nullptr, res, match, match_off, S_out,
+                         S_off, b, st, timed);
+    if (e != 0 || !fp64_final(opt)) return e;
+    // FP64 pass over the pairs whose FP32 result is a near tie (the schedule
+    // arrays are reused: the stream orders the passes)
+    return enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, CFSIM_F64, res, res, match, match_off, S_out, S_off, b,
+                        st, false);
 }
 
 static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -592,6 +684,7 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
         return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
     const bool resize = opt->resize == CFSIM_RESIZE_BILINEAR;
+    if (resize && (s = check_no_fp64_final(opt)) != CFSIM_OK) return s;
     if (resize && (s = check_large_limits(set->max_nodes, opt)) != CFSIM_OK) return s;
     const size_t need = cfsim_batch_workspace_size(ctx, set, n_pairs, opt);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
@@ -701,6 +794,7 @@ cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set, c
         return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
     if ((S_out == nullptr) != (S_off == nullptr))
         return fail(CFSIM_E_INVALID_ARG, "S_out and S_off must both be given or both be NULL");
+    if ((s = check_no_fp64_final(opt)) != CFSIM_OK) return s;
     if ((s = check_large_limits(set->max_nodes, opt)) != CFSIM_OK) return s;
     if (n_pairs == 0) {
         if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
@@ -738,6 +832,8 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
     if (checkpoint_every < 1) return fail(CFSIM_E_INVALID_ARG, "checkpoint_every must be >= 1");
     if (opt->resize == CFSIM_RESIZE_BILINEAR)
         return fail(CFSIM_E_UNSUPPORTED, "the reverse mode runs on the unscaled operator only");
+    if (fp64_final(opt))
+        return fail(CFSIM_E_UNSUPPORTED, "the reverse mode has no FP64 pass (CFSIM_FLAG_FP64_FINAL)");
     if (n_pairs > 0 && (!pair_a || !pair_b || !fwd || !match || !match_off || !grad_score || !grad_w))
         return fail(CFSIM_E_INVALID_ARG, "a pair, forward-result, matching or gradient array is NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");

@@ -172,6 +172,10 @@ struct PairJob {
     // options
     int max_iter;
     double tol;
+    double tie_tol;     // NEAR_TIE threshold on the relative greedy margin
+    // FP64 pass over the near-tie pairs of an FP32 call: a pair runs only if
+    // its FP32 result carries NEAR_TIE; S_out is FP32; status gets FP64_FINAL
+    int refine;
     // outputs
     cfsim_pair_result* res;
     int32_t* match;
@@ -199,6 +203,9 @@ struct PlanJob {
     const int32_t* pair_a;
     const int32_t* pair_b;
     int64_t n_pairs;
+    // if set: only pairs whose result here carries NEAR_TIE (and not
+    // INVALID_INPUT) are planned; the others are left out of every bucket
+    const cfsim_pair_result* filter;
     int esize;
     long long slot_elems;
     int32_t* order;
@@ -261,6 +268,7 @@ struct LargeJob {
     int max_nodes;
     int max_iter;
     double tol;
+    double tie_tol;      // NEAR_TIE threshold on the relative greedy margin
     int resize;          // CFSIM_RESIZE_BILINEAR
     cfsim_pair_result* res;
     int32_t* match;

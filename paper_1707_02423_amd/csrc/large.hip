@@ -17,7 +17,7 @@
 // delta_{k-1} = ||S_{k-1} - S_{k-3}|| is accumulated by the odd launch k, the
 // first one that knows both scales; launch max_iter + 1 only does that.
 //
-// Scale to a common size (Section 3, Section 3.1): the smaller graph X (m
+// Scale to a common size (Section 4 and Section 4.1): the smaller graph X (m
 // nodes) is replaced by X' = R X R^T with the M x m linear-interpolation
 // matrix R.  X' is never formed.  With the small graph on the column side,
 //   Y = Rg S Cg'^T + Rg^T S Cg' = [Rg (S R) Cg^T + Rg^T (S R) Cg] R^T,
@@ -955,6 +955,15 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
         done = now;
     }
 
+    // relative margin of the matching; the picks go to a free slot (a 1 x 1
+    // pair, whose slot holds one element, has no rival anyway)
+    double margin = __builtin_inf();
+    if ((long long)nR + nC <= J.slot_elems) {
+        T* pv = rz ? buf_of<T>(J, p, kSlotV) : buf_of<T>(J, p, (f + 3) & 3);
+        margin = dev::greedy_margin<T, kFinishThreads>(S, nR, nC, false, rstate, cstate, pv, pv + nR, red);
+        __syncthreads();  // red is reused by the score's sum
+    }
+
     const int64_t mo = J.match_off ? J.match_off[p] : 0;
     double sc = 0.0;
     for (int i = tid; i < nR; i += kFinishThreads) {
@@ -971,8 +980,9 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
         res->score = score;
         res->nu = s->nu;
         res->delta = s->delta;
+        res->margin = margin;
         res->iters = f;
-        res->status = s->status;
+        res->status = s->status | (margin <= J.tie_tol ? CFSIM_NEAR_TIE : 0u);
     }
 }
 

@@ -101,11 +101,14 @@ __device__ __forceinline__ void even_terms(EvenSums& s, T y_new, T y_old) {
 
 // Rows of class CLS (order[b..e)) of one update, for the one-wave variant:
 // a class's rows share one straight-line body, no per-row dispatch.
-template <bool EVEN, typename T, int NCH, int CLS>
+template <bool EVEN, typename T, int NT, int NCH, int CLS>
 __device__ __forceinline__ void class_rows(const int* order, int b, int e, const unsigned char* Sb, unsigned char* Nb,
                                            int rowb, const Lists<T>& G, const LaneList<T> (&L)[NCH],
                                            const uint64_t (&ovf)[NCH], bool any_ovf, const int (&col)[NCH],
                                            const bool (&cv)[NCH], T sigma, EvenSums& es) {
+    // b, e come from one LDS word each (the same in every lane) and the loop
+    // has no barrier: both hold only while the workgroup is one wave
+    static_assert(NT == kWave, "class-ordered rows are for one-wave workgroups");
     for (int k = b; k < e; ++k) {
         const int i = uni(order[k]);
         const RowRec<T> rr = G.rec[i];
@@ -132,8 +135,10 @@ __device__ __forceinline__ void class_rows(const int* order, int b, int e, const
 // Rows in class order, stable (ascending row index within a class): order[0..nR)
 // and the class boundaries seg[0..kRowClasses], by the one wave of the
 // workgroup with two ballot passes.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void order_rows(const Lists<T>& G, int nR, int* order, int* seg) {
+    // written by this wave only and read back by it without a barrier
+    static_assert(NT == kWave, "class-ordered rows are for one-wave workgroups");
     const int lane = (int)(threadIdx.x & (kWave - 1));
     int cnt[kRowClasses];
 #pragma unroll
@@ -180,7 +185,7 @@ __device__ __forceinline__ void lds_rows(const unsigned char* Sb, unsigned char*
         // thirteen loop bodies cost more in registers and instruction cache
         // than the dispatch they save)
 #define CFSIM_CLASS_ROWS(C)                                                                                       \
-    class_rows<EVEN, T, NCH, C>(order, uni(seg[C]), uni(seg[(C) + 1]), Sb, Nb, rowb, G, L, ovf, any_ovf, col, cv, \
+    class_rows<EVEN, T, NT, NCH, C>(order, uni(seg[C]), uni(seg[(C) + 1]), Sb, Nb, rowb, G, L, ovf, any_ovf, col, cv, \
                                 sigma, es)
         CFSIM_CLASS_ROWS(0);
         CFSIM_CLASS_ROWS(1);
@@ -291,9 +296,11 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
         }
     }
     if (out.status == 0) out.status = CFSIM_HIT_MAX_ITER;
-    if (sigma != T(1)) {  // S = sigma * Y: every thread scales what it reads next
+    if (sigma != T(1)) {  // S = sigma * Y (sigma is the same in every thread)
         T* Sw = reinterpret_cast<T*>(const_cast<unsigned char*>(Sb));
         for (int t = threadIdx.x; t < nR * nC; t += NT) Sw[t] *= sigma;
+        // the matching reads whole rows across waves
+        __syncthreads();
     }
     out.final_buf = cur;
     return out;
@@ -759,8 +766,22 @@ __device__ __forceinline__ void greedy_rounds(const PairShape& sh, const T* S, T
 
 }
 
+// S (compute orientation, maybe transposed) to the n_B x n_A output.
+template <typename T, typename O, int NT>
+__device__ __forceinline__ void write_S(O* So, const T* S, long long total, int nA, int nC, bool swp) {
+    for (long long o = threadIdx.x; o < total; o += NT) {
+        if (!swp) {
+            So[o] = O(S[o]);
+        } else {
+            const long long i = o / nA, jj = o - i * nA;
+            So[o] = O(S[jj * nC + i]);
+        }
+    }
+}
+
 // Step a7 and the outputs: greedy matching on the stored S (compute
-// orientation), score in original row order, S_out, result.
+// orientation), its relative margin, score in original row order, S_out,
+// result.
 template <typename T, int NT>
 __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const GraphRef& A, const GraphRef& B, const PairShape& sh,
                                  const T* S, T* St, const Lists<T>& G, const IterOut& it, cfsim_pair_result* res,
@@ -775,6 +796,9 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
         greedy_sorted<T, NT>(sh, S, St, G);
     else
         greedy_rounds<T, NT>(sh, S, St, G, s_count);
+    // the row records and column infos are free now: they hold the picks
+    const double margin = greedy_margin<T, NT>(S, sh.nR, nC, swp, rstate, cstate, reinterpret_cast<T*>(G.rec),
+                                               reinterpret_cast<T*>(G.cinfo), red);
 
     const int nA = A.n, nB = B.n;
     const int64_t mo = (J.single || !J.match_off) ? 0 : J.match_off[p];
@@ -794,31 +818,37 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
     }
     if (J.S_out) {
         const int64_t so = (J.single || !J.S_off) ? 0 : J.S_off[p];
-        T* So = reinterpret_cast<T*>(J.S_out) + so;
         const long long total = (long long)nA * nB;
-        for (long long o = tid; o < total; o += NT) {
-            if (!swp) {
-                So[o] = S[o];
-            } else {
-                const long long i = o / nA, jj = o - i * nA;
-                So[o] = S[jj * nC + i];
-            }
-        }
+        // the FP64 pass of an FP32 call writes FP32
+        if (sizeof(T) == 8 && J.refine)
+            write_S<T, float, NT>(reinterpret_cast<float*>(J.S_out) + so, S, total, nA, nC, swp);
+        else
+            write_S<T, T, NT>(reinterpret_cast<T*>(J.S_out) + so, S, total, nA, nC, swp);
     }
     const double score = block_sum<NW>(sc, red + 3 * NW);
     if (tid == 0) {
         res->score = score;
         res->nu = it.nu;
         res->delta = it.delta;
+        res->margin = margin;
         res->iters = it.iters;
-        res->status = it.status;
+        res->status = it.status | (margin <= J.tie_tol ? CFSIM_NEAR_TIE : 0u) | (J.refine ? CFSIM_FP64_FINAL : 0u);
     }
     __syncthreads();
+}
+
+// FP64 pass of an FP32 call: pairs whose FP32 result is not a near tie keep
+// it (the same global word in every thread, so the exit is uniform).
+__device__ inline bool refine_skips(const PairJob& J, int p) {
+    if (!J.refine) return false;
+    const unsigned st = J.res[J.single ? 0 : p].status;
+    return !(st & CFSIM_NEAR_TIE) || (st & CFSIM_INVALID_INPUT);
 }
 
 template <typename T, int NT, int NCHMAX>
 __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count,
                                          int* s_seg) {
+    if (refine_skips(J, p)) return;
     IterOut it;
     {
         GraphRef A{}, B{};
@@ -837,7 +867,7 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
         const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
         const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
         const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
-        if constexpr (NT == kWave) order_rows<T>(G, nR, G.rstate, s_seg);  // one wave: no barrier needed
+        if constexpr (NT == kWave) order_rows<T, NT>(G, nR, G.rstate, s_seg);  // one wave: no barrier needed
         if (NCHMAX == 1 || sh.nchunk == 1)
             it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
         else if (NCHMAX == 2 || sh.nchunk == 2)
@@ -863,6 +893,7 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
 
 template <typename T, int NT>
 __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+    if (refine_skips(J, p)) return;
     GraphRef A{}, B{};
     cfsim_pair_result* res;
     PairShape sh{};
@@ -953,6 +984,13 @@ __device__ void classify(const PlanJob& P, int64_t p, int* bucket, int* cls) {
     const int ga = P.pair_a[p], gb = P.pair_b[p];
     *cls = 0;
     *bucket = kBucketInvalid;
+    if (P.filter) {  // FP64 pass of an FP32 call: near-tie pairs only
+        const unsigned st = P.filter[p].status;
+        if (!(st & CFSIM_NEAR_TIE) || (st & CFSIM_INVALID_INPUT)) {
+            *bucket = -1;
+            return;
+        }
+    }
     if (ga < 0 || ga >= P.set.n_graphs || gb < 0 || gb >= P.set.n_graphs) return;
     const int nA = (int)(P.set.node_off[ga + 1] - P.set.node_off[ga]);
     const int nB = (int)(P.set.node_off[gb + 1] - P.set.node_off[gb]);
@@ -964,6 +1002,10 @@ __device__ void classify(const PlanJob& P, int64_t p, int* bucket, int* cls) {
     for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
         if (choose_shape(nA, nB, mA, mB, v, P.esize, &sh)) b = v;
     if (b == kBucketInvalid && global_fits(nA, nB, mA, mB, P.esize, P.slot_elems, &sh)) b = kBucketGlobal;
+    if (P.filter && b == kBucketInvalid) {  // no FP64 kernel holds it: the FP32 result stays
+        *bucket = -1;
+        return;
+    }
     // longest first: cost class from log2 of the work estimate
     const double work = (double)nA * (double)nB * (1.0 + (double)(mA + mB) / (double)(nA + nB + 1));
     int c = (int)(4.0 * log2(work > 1.0 ? work : 1.0));
@@ -980,7 +1022,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(PlanJob P) {
     for (int64_t p = tid; p < P.n_pairs; p += kPlanThreads) {
         int b, c;
         classify(P, p, &b, &c);
-        atomicAdd(&hist[b * kClasses + c], 1);
+        if (b >= 0) atomicAdd(&hist[b * kClasses + c], 1);
     }
     __syncthreads();
     if (tid == 0) {
@@ -1000,6 +1042,7 @@ __global__ __launch_bounds__(kPlanThreads) void plan_kernel(PlanJob P) {
     for (int64_t p = tid; p < P.n_pairs; p += kPlanThreads) {
         int b, c;
         classify(P, p, &b, &c);
+        if (b < 0) continue;
         const int slot = atomicAdd(&hist[b * kClasses + c], 1);
         P.order[slot] = (int32_t)p;
     }

@@ -70,6 +70,13 @@ __device__ inline double lane_value(double x, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+__device__ inline double wave_fmin(double x) {
+    x = fmin(x, dpp<kDppXor1>(x));
+    x = fmin(x, dpp<kDppXor2>(x));
+    x = fmin(x, dpp<kDppHalfMirror>(x));
+    x = fmin(x, dpp<kDppMirror>(x));
+    return fmin(fmin(lane_value(x, 0), lane_value(x, 16)), fmin(lane_value(x, 32), lane_value(x, 48)));
+}
 __device__ inline double wave_sum(double x) {
     x += dpp<kDppXor1>(x);
     x += dpp<kDppXor2>(x);
@@ -404,6 +411,7 @@ __device__ inline void write_invalid(cfsim_pair_result* r) {
     r->score = __builtin_nan("");
     r->nu = 0.0;
     r->delta = __builtin_inf();
+    r->margin = __builtin_nan("");
     r->iters = 0;
     r->status = CFSIM_INVALID_INPUT;
 }
@@ -730,6 +738,68 @@ __device__ inline double block_sum(double x, double* red) {
     return t;
 }
 
+// Smallest per-thread value over the workgroup (every thread gets it); `red`
+// has NW slots; one barrier.
+template <int NW>
+__device__ inline double block_min(double x, double* red) {
+    x = wave_fmin(x);
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = x;
+    __syncthreads();
+    double t = red[0];
+    for (int w = 1; w < NW; ++w) t = fmin(t, red[w]);
+    return t;
+}
+
+// Relative margin of a finished greedy matching on S (nR x nC, row stride
+// nC; `swp`: S is stored transposed, so the order key of (r, c) is
+// c * nR + r).  A rival of the pick (r, c) is an entry of row r or column c
+// whose other line was still free when (r, c) was taken, that is, its other
+// line is unmatched or matched by a pick later in the greedy order.  The
+// margin is the smallest 1 - q / v over picks v and their rivals q (+inf if
+// there is none); a pick below the smallest normal number of T counts 0 (its
+// relative precision is gone).  Every thread of the workgroup must call it
+// after the matching's last barrier; pv_r[nR] and pv_c[nC] are scratch
+// (free memory the caller owns); one barrier before the reduction.
+template <typename T, int NT>
+__device__ inline double greedy_margin(const T* S, int nR, int nC, bool swp, const int* rstate, const int* cstate,
+                                       T* pv_r, T* pv_c, double* red) {
+    constexpr int NW = NT / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = uni(tid / kWave);
+    for (int r = tid; r < nR; r += NT) {
+        const int c = rstate[r];
+        pv_r[r] = c >= 0 ? S[(long long)r * nC + c] : T(0);
+    }
+    for (int c = tid; c < nC; c += NT) {
+        const int r = cstate[c];
+        pv_c[c] = r >= 0 ? S[(long long)r * nC + c] : T(0);
+    }
+    __syncthreads();
+    const T tiny = sizeof(T) == 8 ? T(DBL_MIN) : T(FLT_MIN);
+    double m = __builtin_inf();
+    for (int r = wave; r < nR; r += NW) {
+        const int pr = uni(rstate[r]);
+        const T va = pv_r[r];
+        const Rank<T> ra = pr >= 0 ? Rank<T>::make(va, (uint32_t)(swp ? pr * nR + r : r * nC + pr)) : Rank<T>::none();
+        const T* line = S + (long long)r * nC;
+        for (int c = lane; c < nC; c += kWave) {
+            if (c == pr) continue;
+            const int pc = cstate[c];
+            const T vb = pv_c[c];
+            bool row_rival = pr >= 0, col_rival = false;
+            if (pc >= 0) {
+                const Rank<T> rb = Rank<T>::make(vb, (uint32_t)(swp ? c * nR + pc : pc * nC + c));
+                row_rival = pr >= 0 && ra < rb;
+                col_rival = !row_rival;
+            }
+            if (row_rival || col_rival) {
+                const T v = row_rival ? va : vb;
+                const double rel = v >= tiny ? 1.0 - (double)line[c] / (double)v : 0.0;
+                m = fmin(m, rel);
+            }
+        }
+    }
+    return block_min<NW>(m, red);
+}
 
 }  // namespace dev
 }  // namespace cfsim

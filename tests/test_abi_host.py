@@ -50,6 +50,9 @@ def _call_score(A, B, opt, res=0x1000, ws=0x1000, ws_bytes=1 << 30):
     ("nan_tol", -1, "tol"),
     ("neg_tol", -1, "tol"),
     ("flags", -1, "flags"),
+    ("fp64_final_f64", -1, "FP32 calls only"),
+    ("nan_tie_tol", -1, "tie_tol"),
+    ("neg_tie_tol", -1, "tie_tol"),
     ("bad_resize", -1, "resize"),
     ("n0", -2, "n must be"),
     ("nnz_neg", -2, "nnz"),
@@ -74,7 +77,13 @@ def test_score_validation(case, code, text):
     elif case == "neg_tol":
         opt.tol = -1.0
     elif case == "flags":
+        opt.flags = 4
+    elif case == "fp64_final_f64":
         opt.flags = 1
+    elif case == "nan_tie_tol":
+        opt.tie_tol = float("nan")
+    elif case == "neg_tie_tol":
+        opt.tie_tol = -1e-3
     elif case == "bad_resize":
         opt.resize = 5
     elif case == "n0":
@@ -252,3 +261,72 @@ def test_resize_workspace_sizes():
     assert L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >= 6 * 16 * 16 * 4
     s = _set(max_nodes=128)
     assert L.cfsim_batch_workspace_size(None, ctypes.byref(s), 100, ctypes.byref(opt)) >= 100 * 6 * 128 * 128 * 4
+
+
+def test_result_and_options_layout():
+    """The ctypes mirrors have the sizes of the C structs (40 and 32 bytes)."""
+    assert cf.RESULT_BYTES == 40 and cf.RESULT_STRIDE == 5
+    assert ctypes.sizeof(cf.Options) == 32
+    assert [n for n, _ in cf.Options._fields_] == ["dtype", "max_iter", "tol", "resize", "flags", "tie_tol"]
+    assert cf.RESULT_DTYPE.names == ("score", "nu", "delta", "margin", "iters", "status")
+
+
+def test_fp64_final_refused_where_it_does_not_apply():
+    L = cf.lib()
+    s = _set()
+    opt = cf.options("f32", resize="bilinear", fp64_final=True)
+    assert L.cfsim_score_batch(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None, None,
+                               None, None, 0x1000, 1 << 40, None) == -6
+    assert "FP64_FINAL" in L.cfsim_last_error().decode()
+    opt = cf.options("f32", fp64_final=True)
+    assert L.cfsim_score_large(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None, None,
+                               None, None, 0x1000, 1 << 40, None) == -6
+    assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
+                                  0x1000, 0x1000, 0x1000, None, 8, 0x1000, 1 << 40, None) == -6
+    # the FP64 pass needs FP64-sized global-kernel slots
+    plain = cf.options("f32")
+    a = L.cfsim_batch_workspace_size(None, ctypes.byref(s), 10, ctypes.byref(plain))
+    b = L.cfsim_batch_workspace_size(None, ctypes.byref(s), 10, ctypes.byref(opt))
+    assert b > a
+    assert (L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(opt)) >=
+            2 * L.cfsim_score_workspace_size(None, 12, 16, ctypes.byref(plain)) - 256)
+
+
+class _G:
+    def __init__(self, n, src, dst, count):
+        self.n, self.src, self.dst, self.count = n, src, dst, count
+
+
+@pytest.mark.parametrize("graphs,code,text", [
+    ([_G(3, [0, 1], [1, 2], [1.0, 2.0]), _G(2, [0], [1], [0.0])], 0, ""),
+    ([_G(3, [0, 1], [1, 3], [1.0, 2.0])], -2, "graph 0, jump 1: endpoint (1, 3) outside [0, 3)"),
+    ([_G(2, [0], [1], [1.0]), _G(2, [-1], [1], [1.0])], -2, "graph 1, jump 0"),
+    ([_G(2, [0, 1], [1, 0], [1.0, float("nan")])], -3, "graph 0, jump 1: count is not finite"),
+    ([_G(2, [0], [1], [float("inf")])], -3, "not finite"),
+    ([_G(4, [0, 1, 2], [1, 2, 3], [1.0, -0.5, 2.0])], -4, "graph 0, jump 1: negative count"),
+    ([_G(1, [], [], [])], 0, ""),
+])
+def test_check_jumps(graphs, code, text):
+    """Host validation returns the documented status and names the first bad jump."""
+    if code == 0:
+        cf.check_jumps(graphs)
+        return
+    with pytest.raises(cf.CfsimError) as e:
+        cf.check_jumps(graphs)
+    assert e.value.code == code and text in str(e.value)
+
+
+def test_check_jumps_offsets():
+    L = cf.lib()
+    import numpy as np
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    no = np.array([0, 2, 2], np.int64)     # second graph has no node
+    eo = np.array([0, 0, 0], np.int64)
+    z = np.zeros(1, np.int32)
+    assert L.cfsim_check_jumps(2, p(no), p(eo), p(z), p(z), p(np.zeros(1))) == -2
+    assert "node_off must increase" in L.cfsim_last_error().decode()
+    no = np.array([0, 2, 4], np.int64)
+    eo = np.array([0, 3, 1], np.int64)     # decreasing edge offsets
+    assert L.cfsim_check_jumps(2, p(no), p(eo), p(z), p(z), p(np.zeros(1))) == -2
+    assert "edge_off decreases" in L.cfsim_last_error().decode()
+    assert L.cfsim_check_jumps(1, None, p(eo), None, None, None) == -1

@@ -4,7 +4,10 @@ import pytest
 
 import oracle
 from cfgsynth import CFG, Grammar, config_graphs, make_cfg
-from tests.parity import check_matching, oracle_pair, rel_err
+from tests.parity import (FP64_FINAL, NEAR_TIE, base_status, check_margin, check_matching, check_S, oracle_pair,
+                          rel_err)
+
+TIE_TOL = {"f64": 1e-12, "f32": 2e-5}
 
 pytestmark = pytest.mark.gpu
 
@@ -70,11 +73,33 @@ def test_pack_equals_oracle_transition_matrices(cf, ctx):
 
 def test_pack_flags_bad_input(cf, ctx):
     bad = [_g(3, [[0, 1, 1], [1, 7, 1]]), _g(2, [[0, 1, float("nan")]]), _g(2, [[0, 1, -2.0]])]
-    for G, flag in zip(bad, [1, 2, 4]):
-        with pytest.raises(ValueError, match="flagged"):
+    for G, flag, code in zip(bad, [1, 2, 4], [-2, -3, -4]):
+        # the host check refuses the lists before anything is uploaded ...
+        with pytest.raises(cf.CfsimError) as e:
             cf.pack(ctx, [G])
+        assert e.value.code == code
+        # ... and the device pack flags them in err_flags when the host check is skipped
         gs = cf.pack(ctx, [G], check=False)
         assert gs is not None
+    from paper_1707_02423_amd import cfsim as cfm
+    import ctypes
+    for G, flag in zip(bad, [1, 2, 4]):
+        node_off, edge_off, src, dst, cnt = cfm.concat_coo([G])
+        t = lambda a, dt: torch.as_tensor(a, dtype=dt).cuda()
+        n, m = int(node_off[-1]), int(edge_off[-1])
+        outs = [torch.empty(n + 1, dtype=torch.int32, device="cuda"), torch.empty(m, dtype=torch.int32, device="cuda"),
+                torch.empty(m, dtype=torch.float64, device="cuda"), torch.empty(n + 1, dtype=torch.int32, device="cuda"),
+                torch.empty(m, dtype=torch.int32, device="cuda"), torch.empty(m, dtype=torch.int32, device="cuda")]
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ws_b = cfm.lib().cfsim_pack_workspace_size(1, n, m)
+        ws = torch.empty(max(ws_b, 1), dtype=torch.uint8, device="cuda")
+        ins = [t(node_off, torch.int64), t(edge_off, torch.int64), t(src, torch.int32), t(dst, torch.int32),
+               t(cnt, torch.float64)]
+        rc = cfm.lib().cfsim_pack(ctx.handle, 1, n, m, *[x.data_ptr() for x in ins], *[x.data_ptr() for x in outs],
+                                  err.data_ptr(), ws.data_ptr(), ws_b, None)
+        assert rc == 0
+        torch.cuda.synchronize()
+        assert int(err.item()) & flag
 
 
 # ------------------------------------------------------------------ plain path
@@ -82,10 +107,10 @@ def _plain_case(cf, ctx, graphs, a, b, dtype, max_iter=200, tol=1e-12):
     gs = cf.pack(ctx, graphs)
     got = cf.score(ctx, gs, a, b, dtype=dtype, max_iter=max_iter, tol=tol)
     ref = oracle_pair(graphs, a, b, max_iter, tol)
-    gate = 1e-10 if dtype == "f64" else 1e-5
-    e = rel_err(got["S"], ref.S)
-    assert e <= gate, f"relative error {e:.3e}"
-    assert got["iters"] == ref.iters and got["status"] == ref.status
+    er = check_S(got["S"], ref.S, dtype)
+    assert got["iters"] == ref.iters and base_status(got["status"]) == ref.status
+    check_margin(got["margin"], got["S"], got["match"], dtype)
+    assert bool(got["status"] & NEAR_TIE) == (got["margin"] <= TIE_TOL[dtype])
     assert abs(got["nu"] - ref.nu) <= (1e-9 if dtype == "f64" else 1e-5) * max(1.0, ref.nu)
     # the kernels take the even-step change from running sums (no stored S_{k-2});
     # it must agree with the oracle's direct ||S_k - S_{k-2}||
@@ -94,7 +119,7 @@ def _plain_case(cf, ctx, graphs, a, b, dtype, max_iter=200, tol=1e-12):
         assert abs(got["delta"] - ref.delta) <= dtol, (got["delta"], ref.delta)
     else:
         assert got["delta"] == float("inf")
-    check_matching(got["S"], got["match"], ref.S)
+    check_matching(got["S"], got["match"], ref.S, dtype, er)
     S64 = got["S"].astype(np.float64)
     assert abs(got["score"] - sum(S64[i, j] for i, j in enumerate(got["match"]) if j >= 0)) < 1e-12
     return got, ref
@@ -147,14 +172,15 @@ def test_plain_oscillating_pair_converges_on_even_step(cf, ctx):
     path = _g(3, [[0, 1, 1], [1, 2, 1]])
     loop = _g(1, [[0, 0, 1]])
     got, ref = _plain_case(cf, ctx, [path, loop], 0, 1, "f64")
-    assert got["iters"] == 2 and got["status"] == cf.CONVERGED
+    assert got["iters"] == 2 and base_status(got["status"]) == cf.CONVERGED
 
 
 def test_plain_degenerate_pair(cf, ctx):
     graphs = [make_cfg(6, Grammar(), seed=1), _g(4, [])]
     gs = cf.pack(ctx, graphs)
     got = cf.score(ctx, gs, 0, 1, dtype="f64")
-    assert got["status"] == cf.DEGENERATE and got["iters"] == 0
+    # every entry of S_0 ties: the margin is 0
+    assert got["status"] == cf.DEGENERATE | cf.NEAR_TIE and got["iters"] == 0 and got["margin"] == 0.0
     np.testing.assert_allclose(got["S"], np.full((4, 6), 1 / np.sqrt(24)), rtol=1e-15)
     assert got["match"].tolist() == [0, 1, 2, 3]
 
@@ -180,19 +206,19 @@ def test_plain_pair_determinism(cf, ctx):
 def _batch_check(cf, ctx, graphs, pa, pb, dtype, sample=None, max_iter=200, tol=1e-12):
     gs = cf.pack(ctx, graphs)
     res, matches, Ss = cf.score_batch(ctx, gs, pa, pb, dtype=dtype, max_iter=max_iter, tol=tol, want_S=True)
-    gate = 1e-10 if dtype == "f64" else 1e-5
     idx = range(len(pa)) if sample is None else sample
     worst, near = 0.0, 0
     for p in idx:
         assert res["status"][p] != cf.INVALID_INPUT, f"pair {p} refused"
         ref = oracle_pair(graphs, int(pa[p]), int(pb[p]), max_iter, tol)
-        e = rel_err(Ss[p], ref.S)
-        worst = max(worst, e)
-        assert e <= gate, f"pair {p}: relative error {e:.3e}"
-        assert res["status"][p] == ref.status or dtype == "f32", f"pair {p} status"
+        er = check_S(Ss[p], ref.S, dtype)
+        worst = max(worst, rel_err(Ss[p], ref.S))
+        assert base_status(res["status"][p]) == ref.status or dtype == "f32", f"pair {p} status"
         if dtype == "f64":
             assert res["iters"][p] == ref.iters
-        near += check_matching(Ss[p], matches[p], ref.S) == "near-tie"
+        check_margin(res["margin"][p], Ss[p], matches[p], dtype)
+        assert bool(res["status"][p] & NEAR_TIE) == (res["margin"][p] <= TIE_TOL[dtype])
+        near += check_matching(Ss[p], matches[p], ref.S, dtype, er) == "near-tie"
         S64 = Ss[p].astype(np.float64)
         assert abs(res["score"][p] - sum(S64[i, j] for i, j in enumerate(matches[p]) if j >= 0)) < 1e-12
     return res, worst, near
@@ -222,9 +248,9 @@ def test_batch_mixed_sizes_every_variant(cf, ctx):
     for p in range(len(pa)):
         nA, nB = sizes[pa[p]], sizes[pb[p]]
         ref = oracle_pair(graphs, int(pa[p]), int(pb[p]))
-        e = rel_err(Ss[p], ref.S)
-        assert e <= 1e-5, (p, nA, nB, e)
-        check_matching(Ss[p], matches[p], ref.S)
+        er = check_S(Ss[p], ref.S, "f32")
+        check_margin(res["margin"][p], Ss[p], matches[p], "f32")
+        check_matching(Ss[p], matches[p], ref.S, "f32", er)
 
 
 def test_batch_invalid_indices_and_empty(cf, ctx):
@@ -234,7 +260,7 @@ def test_batch_invalid_indices_and_empty(cf, ctx):
     pb = np.array([1, 0, 2, 2], np.int32)
     res, matches, _ = cf.score_batch(ctx, gs, pa, pb, dtype="f32", want_match=False)
     assert res["status"][1] == cf.INVALID_INPUT and res["status"][2] == cf.INVALID_INPUT
-    assert res["status"][0] in (cf.CONVERGED, cf.HIT_MAX_ITER)
+    assert base_status(res["status"][0]) in (cf.CONVERGED, cf.HIT_MAX_ITER)
     r0, _, _ = cf.score_batch(ctx, gs, np.zeros(0, np.int32), np.zeros(0, np.int32), want_match=False)
     assert len(r0) == 0
 
@@ -260,8 +286,8 @@ def test_batch_matches_plain_path(cf, ctx):
     res, matches, Ss = cf.score_batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", want_S=True)
     for p in range(len(res)):
         r = cf.score(ctx, gs, int(w["pair_a"][p]), int(w["pair_b"][p]), dtype="f64")
-        assert rel_err(r["S"], Ss[p]) < 1e-13
-        assert np.array_equal(r["match"], matches[p])
+        assert np.array_equal(r["S"], Ss[p])  # same kernels, same order of arithmetic
+        assert np.array_equal(r["match"], matches[p]) and r["margin"] == res["margin"][p]
 
 
 def test_workload1_full_size_sampled(cf, ctx):
@@ -286,9 +312,10 @@ def test_workload1_full_size_sampled(cf, ctx):
         S = S_all[o:o + nA * nB].cpu().numpy().reshape(nB, nA)
         assert abs(np.linalg.norm(S.astype(np.float64)) - 1) < 1e-5
         ref = oracle_pair(w["graphs"], int(w["pair_a"][p]), int(w["pair_b"][p]))
-        assert rel_err(S, ref.S) <= 1e-5
+        er = check_S(S, ref.S, "f32")
         m = b.match[int(b.match_off_h[p]):int(b.match_off_h[p]) + nB].cpu().numpy()
-        check_matching(S, m, ref.S)
+        check_margin(res["margin"][p], S, m, "f32")
+        check_matching(S, m, ref.S, "f32", er)
 
 
 def test_batch_buckets_and_timed_launch(cf, ctx):
@@ -321,3 +348,55 @@ def test_batch_buckets_and_timed_launch(cf, ctx):
     assert ms.shape == (cf.NUM_BUCKETS,) and np.all(ms >= 0)
     assert np.all(ms[used] > 0), ms
     assert np.all(r_graph["status"][bk == 6] == cf.INVALID_INPUT)
+
+
+# ------------------------------------------------------------------ FP64 pass of FP32 calls
+def test_fp64_final_batch_replaces_near_ties(cf, ctx):
+    """CFSIM_FLAG_FP64_FINAL: the near-tie pairs of an FP32 batch carry the
+    FP64 results (bit for bit those of an FP64 batch), every other pair its
+    FP32 result (bit for bit those of a plain FP32 batch)."""
+    w = config_graphs(1, scale=20 / 256)
+    gs = cf.pack(ctx, w["graphs"])
+    pa, pb = w["pair_a"], w["pair_b"]
+    r32, m32, S32 = cf.score_batch(ctx, gs, pa, pb, dtype="f32", want_S=True)
+    r64, m64, S64 = cf.score_batch(ctx, gs, pa, pb, dtype="f64", want_S=True)
+    rf, mf, Sf = cf.score_batch(ctx, gs, pa, pb, dtype="f32", want_S=True, fp64_final=True)
+    near = (r32["status"] & NEAR_TIE) != 0
+    assert near.any() and not near.all()
+    assert np.array_equal((rf["status"] & FP64_FINAL) != 0, near)
+    for p in range(len(pa)):
+        if near[p]:
+            for k in ("score", "nu", "delta", "margin", "iters", "status"):
+                want = r64[k][p] | (FP64_FINAL if k == "status" else 0)
+                assert rf[k][p] == want, (p, k, rf[k][p], want)
+            assert np.array_equal(mf[p], m64[p])
+            assert np.array_equal(Sf[p], S64[p].astype(np.float32))
+        else:
+            assert rf[p].tobytes() == r32[p].tobytes()
+            assert np.array_equal(mf[p], m32[p]) and np.array_equal(Sf[p], S32[p])
+    # FP64-finalised pairs agree with the oracle's matching under the FP64 contract
+    for p in np.flatnonzero(near)[:12]:
+        ref = oracle_pair(w["graphs"], int(pa[p]), int(pb[p]))
+        er = check_S(S64[p], ref.S, "f64")
+        check_matching(S64[p], mf[p], ref.S, "f64", er)
+
+
+def test_fp64_final_single_pair(cf, ctx):
+    # two copies of one CFG: symmetric S, exact ties between mirrored entries
+    g = make_cfg(24, Grammar(counts="trip"), seed=9)
+    gs = cf.pack(ctx, [g, g, make_cfg(30, Grammar(counts="trip"), seed=10)])
+    r32 = cf.score(ctx, gs, 0, 1, dtype="f32")
+    rf = cf.score(ctx, gs, 0, 1, dtype="f32", fp64_final=True)
+    r64 = cf.score(ctx, gs, 0, 1, dtype="f64")
+    if r32["status"] & NEAR_TIE:
+        assert rf["status"] == r64["status"] | FP64_FINAL
+        assert rf["score"] == r64["score"] and np.array_equal(rf["match"], r64["match"])
+        assert np.array_equal(rf["S"], r64["S"].astype(np.float32))
+    else:
+        assert rf["status"] == r32["status"] and np.array_equal(rf["S"], r32["S"])
+    # a pair without a near tie keeps its FP32 result
+    for a, b in ((0, 2), (2, 0)):
+        q32 = cf.score(ctx, gs, a, b, dtype="f32")
+        qf = cf.score(ctx, gs, a, b, dtype="f32", fp64_final=True)
+        if not q32["status"] & NEAR_TIE:
+            assert qf["status"] == q32["status"] and np.array_equal(qf["S"], q32["S"])

@@ -60,14 +60,40 @@ def test_mutant_update_count_fails_the_eigen_pin(monkeypatch):
     assert not _closed_form_holds(A, B)
 
 
+def _naive_greedy(S):
+    """The pin: repeatedly the largest free entry, ties to the smaller flat
+    index, by a plain double loop (no sorting)."""
+    S = np.asarray(S, np.float64)
+    nB, nA = S.shape
+    rows, cols = set(range(nB)), set(range(nA))
+    match = np.full(nB, -1)
+    while rows and cols:
+        best = None
+        for i in sorted(rows):
+            for j in sorted(cols):
+                if best is None or S[i, j] > S[best]:
+                    best = (i, j)
+        match[best[0]] = best[1]
+        rows.discard(best[0])
+        cols.discard(best[1])
+    return match
+
+
+def _greedy_pin_holds(cases):
+    return all(np.array_equal(ref.greedy_match(S)[0], _naive_greedy(S)) for S in cases)
+
+
 def test_mutant_tie_break_fails_the_naive_greedy_pin(monkeypatch):
-    S = np.array([[1.0, 1.0], [1.0, 0.0]])
+    """A reversed tie-break planted into the oracle's greedy fails the pin."""
+    rng = np.random.default_rng(4)
+    cases = [np.array([[1.0, 1.0], [1.0, 0.0]]), np.round(rng.random((5, 4)), 1), np.ones((3, 3))]
+    assert _greedy_pin_holds(cases)
 
     def reversed_ties(S):
         nB, nA = S.shape
-        flat = S.ravel()
+        flat = np.asarray(S, np.float64).ravel()
         order = np.lexsort((-np.arange(flat.size), -flat))
-        used_r, used_c, match = set(), set(), np.full(nB, -1)
+        used_r, used_c, match = set(), set(), np.full(nB, -1, np.int32)
         for idx in order:
             i, j = divmod(int(idx), nA)
             if i not in used_r and j not in used_c:
@@ -75,8 +101,8 @@ def test_mutant_tie_break_fails_the_naive_greedy_pin(monkeypatch):
                 used_r.add(i)
                 used_c.add(j)
         return match, 0.0
-    assert oracle.greedy_match(S)[0].tolist() == [0, 1]
-    assert reversed_ties(S)[0].tolist() == [1, 0]
+    monkeypatch.setattr(ref, "greedy_match", reversed_ties)
+    assert not _greedy_pin_holds(cases)
 
 
 def test_mutant_backward_fails_finite_differences(monkeypatch):
