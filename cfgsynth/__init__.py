@@ -5,7 +5,7 @@ and integer execution counts on the edges.  It performs none of the
 similarity arithmetic (no normalisation, no resize, no iteration), so both
 the CPU oracle and the HIP path can consume its output.
 
-CFG shape (paper Section 2, "Kernel Control Flow Graphs"): a directed graph
+CFG shape (paper Section 3, Background, "Kernel Control Flow Graphs"): a directed graph
 with a unique START node from which every node is reachable and a unique
 STOP node; nodes are basic blocks, edges are jumps.  The paper calls it
 acyclic, but kernels are dominated by loops (abstract), so back-edges and

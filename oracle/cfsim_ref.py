@@ -7,11 +7,11 @@ It shares no code with the HIP library and imports nothing from it.
 Method (Lim, Norris & Malony, "A Similarity Measure for GPU Kernel Subgraph
 Matching", arXiv 1707.02423):
 
-* Section 2, "Transition probability": each CFG becomes a right-stochastic
+* Section 3 (Background), "Transition probability": each CFG becomes a right-stochastic
   transition matrix, P[i, j] = Pr(j | i), every non-empty row sums to 1.
-* Section 3 and Section 3.1: the smaller matrix is interpolated up to the
+* Section 4 (Methodology) and Section 4.1 (Bilinear Interpolation): the smaller matrix is interpolated up to the
   larger size with an order-1 (bilinear) spline before comparison.
-* Table 1, row "Iso", and Section 3.2: graphs are compared by the IsoRank
+* Table 1, row "Iso", and Section 4.2 (Pairwise Comparison): graphs are compared by the IsoRank
   solution of the Kronecker operator of the two matrices.
 
 Readings taken where the paper is silent or garbled (each is listed in the
@@ -50,7 +50,7 @@ INVALID_INPUT = 8
 
 
 # --------------------------------------------------------------------------
-# Step a1: transition-probability matrices (Section 2, "Transition probability")
+# Step a1: transition-probability matrices (Section 3, "Transition probability")
 # --------------------------------------------------------------------------
 def transition_matrix(n: int, src, dst, count) -> np.ndarray:
     """Dense right-stochastic matrix of one CFG.
@@ -81,7 +81,7 @@ def transition_matrix_sparse(n: int, src, dst, count) -> sp.csr_matrix:
 
 
 # --------------------------------------------------------------------------
-# Step a2: scale to a common size (Section 3, Section 3.1)
+# Step a2: scale to a common size (Section 4, Section 4.1)
 # --------------------------------------------------------------------------
 def _interp_matrix(m: int, M: int):
     """M x m matrix of 1-D linear interpolation at p (m-1)/(M-1)."""
@@ -116,7 +116,7 @@ def resize_bilinear(X, M: int):
 
 
 # --------------------------------------------------------------------------
-# Steps a3-a6: coupled iteration (Table 1 "Iso", Section 3.2)
+# Steps a3-a6: coupled iteration (Table 1 "Iso", Section 4.2)
 # --------------------------------------------------------------------------
 def apply_operator(A, B, S: np.ndarray) -> np.ndarray:
     """Y = B S A^T + B^T S A, the Kronecker operator (B (x) A + B^T (x) A^T)
@@ -173,7 +173,7 @@ def coupled_iteration(A, B, max_iter: int = 200, tol: float = 1e-12, keep_iterat
 
 
 # --------------------------------------------------------------------------
-# Step a7: score and node matching (Section 3.2; IsoRank's greedy extraction)
+# Step a7: score and node matching (Section 4.2; IsoRank's greedy extraction)
 # --------------------------------------------------------------------------
 def greedy_match(S: np.ndarray):
     """Greedy matching: repeatedly take the largest S[i, j] whose row and

@@ -1,4 +1,4 @@
-// Step a1: transition-probability matrices of a set of CFGs (paper Section 2,
+// Step a1: transition-probability matrices of a set of CFGs (paper Section 3,
 // "Transition probability": P[u][v] = Pr(v | u), each non-empty row sums to 1).
 //
 // One workgroup per graph builds, from the graph's jump list with execution

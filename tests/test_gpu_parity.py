@@ -4,8 +4,8 @@ import pytest
 
 import oracle
 from cfgsynth import CFG, Grammar, config_graphs, make_cfg
-from tests.parity import (FP64_FINAL, NEAR_TIE, base_status, check_margin, check_matching, check_S, oracle_pair,
-                          rel_err)
+from tests.parity import (FP64_FINAL, NEAR_TIE, base_status, chain_depth, check_margin, check_matching, check_S,
+                          oracle_pair, rel_err, stop_drift)
 
 TIE_TOL = {"f64": 1e-12, "f32": 2e-5}
 
@@ -107,7 +107,8 @@ def _plain_case(cf, ctx, graphs, a, b, dtype, max_iter=200, tol=1e-12):
     gs = cf.pack(ctx, graphs)
     got = cf.score(ctx, gs, a, b, dtype=dtype, max_iter=max_iter, tol=tol)
     ref = oracle_pair(graphs, a, b, max_iter, tol)
-    er = check_S(got["S"], ref.S, dtype)
+    er = check_S(got["S"], ref.S, dtype, max(got["iters"], ref.iters), chain_depth(graphs[a], graphs[b]),
+                 stop_drift(graphs, a, b, got["iters"], ref.iters))
     assert got["iters"] == ref.iters and base_status(got["status"]) == ref.status
     check_margin(got["margin"], got["S"], got["match"], dtype)
     assert bool(got["status"] & NEAR_TIE) == (got["margin"] <= TIE_TOL[dtype])
@@ -211,7 +212,8 @@ def _batch_check(cf, ctx, graphs, pa, pb, dtype, sample=None, max_iter=200, tol=
     for p in idx:
         assert res["status"][p] != cf.INVALID_INPUT, f"pair {p} refused"
         ref = oracle_pair(graphs, int(pa[p]), int(pb[p]), max_iter, tol)
-        er = check_S(Ss[p], ref.S, dtype)
+        er = check_S(Ss[p], ref.S, dtype, max(res["iters"][p], ref.iters), chain_depth(graphs[pa[p]], graphs[pb[p]]),
+                     stop_drift(graphs, pa[p], pb[p], res["iters"][p], ref.iters))
         worst = max(worst, rel_err(Ss[p], ref.S))
         assert base_status(res["status"][p]) == ref.status or dtype == "f32", f"pair {p} status"
         if dtype == "f64":
@@ -248,7 +250,8 @@ def test_batch_mixed_sizes_every_variant(cf, ctx):
     for p in range(len(pa)):
         nA, nB = sizes[pa[p]], sizes[pb[p]]
         ref = oracle_pair(graphs, int(pa[p]), int(pb[p]))
-        er = check_S(Ss[p], ref.S, "f32")
+        er = check_S(Ss[p], ref.S, "f32", max(res["iters"][p], ref.iters), chain_depth(graphs[pa[p]], graphs[pb[p]]),
+                     stop_drift(graphs, pa[p], pb[p], res["iters"][p], ref.iters))
         check_margin(res["margin"][p], Ss[p], matches[p], "f32")
         check_matching(Ss[p], matches[p], ref.S, "f32", er)
 
@@ -311,8 +314,10 @@ def test_workload1_full_size_sampled(cf, ctx):
         o, nA, nB = int(b.S_off_h[p]), int(b.nA[p]), int(b.nB[p])
         S = S_all[o:o + nA * nB].cpu().numpy().reshape(nB, nA)
         assert abs(np.linalg.norm(S.astype(np.float64)) - 1) < 1e-5
-        ref = oracle_pair(w["graphs"], int(w["pair_a"][p]), int(w["pair_b"][p]))
-        er = check_S(S, ref.S, "f32")
+        ga, gb = int(w["pair_a"][p]), int(w["pair_b"][p])
+        ref = oracle_pair(w["graphs"], ga, gb)
+        er = check_S(S, ref.S, "f32", max(res["iters"][p], ref.iters), chain_depth(w["graphs"][ga], w["graphs"][gb]),
+                     stop_drift(w["graphs"], ga, gb, res["iters"][p], ref.iters))
         m = b.match[int(b.match_off_h[p]):int(b.match_off_h[p]) + nB].cpu().numpy()
         check_margin(res["margin"][p], S, m, "f32")
         check_matching(S, m, ref.S, "f32", er)
@@ -367,7 +372,7 @@ def test_fp64_final_batch_replaces_near_ties(cf, ctx):
     for p in range(len(pa)):
         if near[p]:
             for k in ("score", "nu", "delta", "margin", "iters", "status"):
-                want = r64[k][p] | (FP64_FINAL if k == "status" else 0)
+                want = (r64[k][p] | FP64_FINAL) if k == "status" else r64[k][p]
                 assert rf[k][p] == want, (p, k, rf[k][p], want)
             assert np.array_equal(mf[p], m64[p])
             assert np.array_equal(Sf[p], S64[p].astype(np.float32))

@@ -1,4 +1,4 @@
-"""Parity of the scale-to-common-size mode (bilinear resize, Section 3.1)
+"""Parity of the scale-to-common-size mode (bilinear resize, Section 4.1)
 with the FP64 oracle, through cfsim_score and cfsim_score_batch."""
 import numpy as np
 import pytest
