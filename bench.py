@@ -548,8 +548,10 @@ def main():
         # per-entry relative error)
         S32h, S64h = b32.S.cpu().numpy(), b64.S.cpu().numpy()
 
+        S_off_h, nA_h, nB_h = np.array(b32.S_off_h), np.array(b32.nA), np.array(b32.nB)
+
         def pair_S(p):
-            o, a, b_ = int(b32.S_off_h[p]), int(b32.nA[p]), int(b32.nB[p])
+            o, a, b_ = int(S_off_h[p]), int(nA_h[p]), int(nB_h[p])
             return S32h[o:o + a * b_].reshape(b_, a), S64h[o:o + a * b_].reshape(b_, a)
         diff = np.flatnonzero(~same)
         certified = 0
