@@ -209,6 +209,27 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
                          cfsim_pair_result* res, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * cfsim_score without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments (minus ws,
+ * ws_bytes), kernels, outputs and per-pair semantics as cfsim_score; the
+ * workspace is a static device array of CFSIM_NOALLOC_SCRATCH_BYTES that
+ * each GPU holds until the process ends (its address is taken once per
+ * device by cfsim_context_create).  The call allocates nothing: a pair whose
+ * cfsim_score_workspace_size exceeds CFSIM_NOALLOC_SCRATCH_BYTES (FP64
+ * beyond about 1,000 x 1,000 nodes, FP32 beyond about 1,400 x 1,400; less
+ * when resized or with CFSIM_FLAG_FP64_FINAL) returns CFSIM_E_UNSUPPORTED
+ * before any HIP call.  Every call on one GPU shares that GPU's scratch and
+ * leaves it holding its own intermediate data (the kernels initialise
+ * everything they read): calls that overlap on one GPU (several streams or
+ * host threads) race, so serialise them.
+ */
+#define CFSIM_NOALLOC_SCRATCH_BYTES (16 << 20)
+cfsim_status cfsim_score_noalloc(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B,
+                                 const cfsim_options* opt, void* S_out, int32_t* match_out,
+                                 cfsim_pair_result* res, void* stream);
+
+/*
  * Steps a2-a8 for many pairs (batched path): pair p compares A = graph
  * pair_a[p] with B = graph pair_b[p] of `set`.  The pairs are planned on the
  * device (size buckets, longest first) and run by persistent workgroups

@@ -23,6 +23,7 @@ CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, NEAR_TIE, FP64_FINAL = 1, 2,
 FLAG_FP64_FINAL = 1
 NUM_BUCKETS = 7  # batch buckets: 0-4 LDS kernels, 5 global-memory kernel, 6 invalid pairs
 PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
+NOALLOC_SCRATCH_BYTES = 16 << 20  # CFSIM_NOALLOC_SCRATCH_BYTES
 
 STATUS_NAMES = {0: "CFSIM_OK", -1: "CFSIM_E_INVALID_ARG", -2: "CFSIM_E_BAD_GRAPH", -3: "CFSIM_E_NONFINITE",
                 -4: "CFSIM_E_NEGWEIGHT", -5: "CFSIM_E_WORKSPACE", -6: "CFSIM_E_UNSUPPORTED", -7: "CFSIM_E_HIP"}
@@ -76,6 +77,8 @@ SIGNATURES = {
     "cfsim_score_workspace_size": (_SZ, [_P, _I32, _I32, ctypes.POINTER(Options)]),
     "cfsim_score": (ctypes.c_int, [_P, ctypes.POINTER(Graph), ctypes.POINTER(Graph), ctypes.POINTER(Options), _P, _P,
                                    _P, _P, _SZ, _P]),
+    "cfsim_score_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(Graph), ctypes.POINTER(Graph), ctypes.POINTER(Options),
+                                           _P, _P, _P, _P]),
     "cfsim_batch_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options)]),
     "cfsim_score_batch": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
                                          _P, _P, _P, _P, _P, _SZ, _P]),

@@ -6,10 +6,18 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "cfsim_internal.h"
+
+// Device scratch of cfsim_score_noalloc: the workspace of cfsim_score, held
+// by every GPU the library runs on until the process ends.  In host code
+// `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress (once per device, at context creation) and only that
+// address is ever handed to kernels.
+static __device__ __align__(256) unsigned char scratch[CFSIM_NOALLOC_SCRATCH_BYTES];
 
 struct cfsim_context {
     int device = 0;
@@ -26,11 +34,33 @@ struct cfsim_context {
     int timed = 0;                          // a timed call has been enqueued
     hipEvent_t t0[cfsim::kBuckets] = {};
     hipEvent_t t1[cfsim::kBuckets] = {};
+    void* scratch = nullptr;                // this device's copy of `scratch`
 };
 
 namespace {
 
 thread_local std::string g_err;
+
+// Device address of `scratch` per device, taken once per device.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// With `device` current: its address of `scratch` (NULL for device ids past
+// the table).  Returns a HIP error code.
+int scratch_address(int device, void** out) {
+    *out = nullptr;
+    if (device >= kMaxScratchDevices) return 0;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        const int e = (int)hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != 0) return e;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return 0;
+}
 
 cfsim_status fail(cfsim_status s, const char* fmt, ...) {
     char buf[512];
@@ -359,6 +389,10 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device) {
             ctx->grid[d][v] = ctx->num_cus * blocks;
         }
     }
+    if ((e = scratch_address(device, &ctx->scratch)) != 0) {
+        delete ctx;
+        return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    }
     if ((e = (int)hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking)) != 0) {
         delete ctx;
         return hip_fail(e, "hipStreamCreateWithFlags");
@@ -548,6 +582,24 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
         if (e != 0) return hip_fail(e, "FP64 pass launch");
     }
     return ok();
+}
+
+cfsim_status cfsim_score_noalloc(cfsim_context* ctx, const cfsim_graph* A, const cfsim_graph* B,
+                                 const cfsim_options* opt, void* S_out, int32_t* match_out, cfsim_pair_result* res,
+                                 void* stream) {
+    cfsim_status s;
+    if ((s = check_graph(A, "A")) != CFSIM_OK) return s;
+    if ((s = check_graph(B, "B")) != CFSIM_OK) return s;
+    if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    const size_t need = cfsim_score_workspace_size(ctx, A->n, B->n, opt);
+    if (need > (size_t)CFSIM_NOALLOC_SCRATCH_BYTES)
+        return fail(CFSIM_E_UNSUPPORTED, "pair %d x %d needs %zu bytes of scratch; the static scratch holds %zu",
+                    B->n, A->n, need, (size_t)CFSIM_NOALLOC_SCRATCH_BYTES);
+    if (!ctx->scratch) return fail(CFSIM_E_UNSUPPORTED, "no static scratch on device %d", ctx->device);
+    return cfsim_score(ctx, A, B, opt, S_out, match_out, res, ctx->scratch, (size_t)CFSIM_NOALLOC_SCRATCH_BYTES,
+                       stream);
 }
 
 // ------------------------------------------------------------------ batch (a2-a8)

@@ -330,3 +330,24 @@ def test_check_jumps_offsets():
     assert L.cfsim_check_jumps(2, p(no), p(eo), p(z), p(z), p(np.zeros(1))) == -2
     assert "edge_off decreases" in L.cfsim_last_error().decode()
     assert L.cfsim_check_jumps(1, None, p(eo), None, None, None) == -1
+
+
+def test_score_noalloc_validation():
+    """The no-allocation entry point checks its arguments, then its scratch
+    bound, on the host before any HIP call."""
+    L = cf.lib()
+    A, B = _graph(), _graph(4, 3)
+    opt = cf.options("f64")
+    call = lambda ctx, A, B, opt, res: L.cfsim_score_noalloc(
+        ctx, ctypes.byref(A) if A is not None else None, ctypes.byref(B), ctypes.byref(opt) if opt else None,
+        None, None, res, None)
+    assert call(None, None, B, opt, 0x1000) == -1 and "NULL" in L.cfsim_last_error().decode()
+    assert call(None, A, B, None, 0x1000) == -1 and "options" in L.cfsim_last_error().decode()
+    assert call(None, A, B, opt, None) == -1 and "res" in L.cfsim_last_error().decode()
+    assert call(None, A, B, opt, 0x1000) == -1 and "context" in L.cfsim_last_error().decode()
+    # past the scratch: FP64 2 * n_A * n_B * 8 bytes > 16 MiB
+    big_a, big_b = _graph(1500, 2000), _graph(1400, 1900)
+    assert L.cfsim_score_workspace_size(None, 1500, 1400, ctypes.byref(opt)) > cf.NOALLOC_SCRATCH_BYTES
+    got = L.cfsim_score_noalloc(ctypes.c_void_p(0x1000), ctypes.byref(big_a), ctypes.byref(big_b),
+                                ctypes.byref(opt), None, None, 0x1000, None)
+    assert got == -6 and "static scratch" in L.cfsim_last_error().decode()
