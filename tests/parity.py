@@ -90,10 +90,11 @@ def stop_drift(graphs, a, b, k_gpu, k_ref):
     if k_gpu == k_ref:
         return 0.0
     ga, gb = graphs[a], graphs[b]
-    A = oracle.transition_matrix(ga.n, ga.src, ga.dst, ga.count)
-    B = oracle.transition_matrix(gb.n, gb.src, gb.dst, gb.count)
+    mat = oracle.transition_matrix_sparse if max(ga.n, gb.n) > 128 else oracle.transition_matrix
+    A = mat(ga.n, ga.src, ga.dst, ga.count)
+    B = mat(gb.n, gb.src, gb.dst, gb.count)
     its = oracle.coupled_iteration(A, B, max(k_gpu, k_ref), 0.0, keep_iterates=True)[5]
-    return np.abs(its[k_gpu] - its[k_ref])
+    return np.abs(np.asarray(its[k_gpu]) - np.asarray(its[k_ref]))
 
 
 def check_S(S_gpu, S_ref, dtype, iters=200, depth=DEFAULT_DEPTH, drift=0.0):

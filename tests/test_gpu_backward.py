@@ -103,6 +103,8 @@ def test_autograd_function_matches_finite_differences(cf, ctx):
     b.run()
     torch.cuda.synchronize()
     res, matches = b.results(), b.matches()
+    # the FD of one pair is compared with the summed gradient: no graph may be shared
+    assert len(set(pa.tolist()) | set(pb.tolist())) == 2 * len(pa)
     rng = np.random.default_rng(3)
     h = 1e-6
     from paper_1707_02423_amd.cfsim import concat_coo
