@@ -82,6 +82,19 @@ enum { CFSIM_RESIZE_NONE = 0, CFSIM_RESIZE_BILINEAR = 1 };
                                     (rounded to FP32), nu, delta, margin, iters
                                     and status are replaced by the FP64 ones   */
 
+#define CFSIM_FLAG_MFMA_BF16 2u  /* cfsim_score_large, FP32, no resize: the
+                                    operator products run as block-sparse
+                                    BF16 matrix-core products with FP32
+                                    accumulation (32 x 32 blocks of A, B and S
+                                    rounded to BF16; Y, norms, the even-step
+                                    test and the matching in FP32/FP64).  A
+                                    graph with more nonzero 32 x 32 blocks than
+                                    twice the largest node count of the set
+                                    gives its pair CFSIM_INVALID_INPUT.  The
+                                    results are not gated against FP64: their
+                                    error is of the order of BF16 rounding
+                                    (Table 1 "Iso" with dense padded tiles)   */
+
 /* Pack error bits written by cfsim_pack into *err_flags. */
 #define CFSIM_PACK_BAD_INDEX 1  /* a jump endpoint outside [0, n_g): dropped   */
 #define CFSIM_PACK_NONFINITE 2  /* a count is NaN or infinite: weight set to 0 */

@@ -4,7 +4,8 @@ Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
 `bench.py` may import or call anything in this package.  The product path
 (the HIP library and its Python binding) never touches it, and this package
 imports nothing from the product.  See `oracle/cfsim_ref.py` for the
-readings of the paper it implements.
+readings of the paper it implements, and `oracle/bf16_model.py` for the
+model of the BF16 matrix-core variant.
 """
 from .cfsim_ref import (  # noqa: F401
     CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT,
@@ -12,3 +13,4 @@ from .cfsim_ref import (  # noqa: F401
     apply_operator, coupled_iteration, greedy_match, score_pair,
     backward, edge_gradients, topk, PairResult,
 )
+from .bf16_model import round_bf16, coupled_iteration_bf16  # noqa: F401

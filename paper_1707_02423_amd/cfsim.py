@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 RESIZE_NONE, RESIZE_BILINEAR = 0, 1
 CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT, NEAR_TIE, FP64_FINAL = 1, 2, 4, 8, 16, 32
 FLAG_FP64_FINAL = 1
+FLAG_MFMA_BF16 = 2
 NUM_BUCKETS = 7  # batch buckets: 0-4 LDS kernels, 5 global-memory kernel, 6 invalid pairs
 PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
 NOALLOC_SCRATCH_BYTES = 16 << 20  # CFSIM_NOALLOC_SCRATCH_BYTES
@@ -129,11 +130,12 @@ def _stream(stream) -> int | None:
     return stream.cuda_stream or None
 
 
-def options(dtype="f64", max_iter=200, tol=1e-12, resize="none", tie_tol=0.0, fp64_final=False) -> Options:
+def options(dtype="f64", max_iter=200, tol=1e-12, resize="none", tie_tol=0.0, fp64_final=False,
+            mfma=False) -> Options:
     d = {"f64": F64, "f32": F32}[dtype] if isinstance(dtype, str) else int(dtype)
     r = {"none": RESIZE_NONE, "bilinear": RESIZE_BILINEAR}[resize] if isinstance(resize, str) else int(resize)
-    return Options(dtype=d, max_iter=int(max_iter), tol=float(tol), resize=r,
-                   flags=FLAG_FP64_FINAL if fp64_final else 0, tie_tol=float(tie_tol))
+    flags = (FLAG_FP64_FINAL if fp64_final else 0) | (FLAG_MFMA_BF16 if mfma else 0)
+    return Options(dtype=d, max_iter=int(max_iter), tol=float(tol), resize=r, flags=flags, tie_tol=float(tie_tol))
 
 
 class Context:
@@ -318,12 +320,12 @@ class Batch:
 
     def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
                  resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch",
-                 tie_tol=0.0, fp64_final=False):
+                 tie_tol=0.0, fp64_final=False, mfma=False):
         if path not in ("batch", "large"):
             raise ValueError("path must be 'batch' (cfsim_score_batch) or 'large' (cfsim_score_large)")
         self.path = path
         self.ctx, self.gs = ctx, gs
-        self.opt = options(dtype, max_iter, tol, resize, tie_tol, fp64_final)
+        self.opt = options(dtype, max_iter, tol, resize, tie_tol, fp64_final, mfma)
         dev = gs.w.device
         self.pair_a_h = np.asarray(pair_a, np.int32)
         self.pair_b_h = np.asarray(pair_b, np.int32)

@@ -92,10 +92,14 @@ cfsim_status check_options(const cfsim_options* o) {
         return fail(CFSIM_E_INVALID_ARG, "tol must be finite and >= 0");
     if (o->resize != CFSIM_RESIZE_NONE && o->resize != CFSIM_RESIZE_BILINEAR)
         return fail(CFSIM_E_INVALID_ARG, "resize must be CFSIM_RESIZE_NONE or CFSIM_RESIZE_BILINEAR");
-    if ((o->flags & ~CFSIM_FLAG_FP64_FINAL) != 0)
-        return fail(CFSIM_E_INVALID_ARG, "flags: unknown bits %#x", o->flags & ~CFSIM_FLAG_FP64_FINAL);
+    const uint32_t known = CFSIM_FLAG_FP64_FINAL | CFSIM_FLAG_MFMA_BF16;
+    if ((o->flags & ~known) != 0) return fail(CFSIM_E_INVALID_ARG, "flags: unknown bits %#x", o->flags & ~known);
     if ((o->flags & CFSIM_FLAG_FP64_FINAL) && o->dtype != CFSIM_F32)
         return fail(CFSIM_E_INVALID_ARG, "CFSIM_FLAG_FP64_FINAL applies to FP32 calls only");
+    if ((o->flags & CFSIM_FLAG_MFMA_BF16) && (o->dtype != CFSIM_F32 || o->resize != CFSIM_RESIZE_NONE))
+        return fail(CFSIM_E_INVALID_ARG, "CFSIM_FLAG_MFMA_BF16 applies to FP32 calls without resize only");
+    if ((o->flags & CFSIM_FLAG_MFMA_BF16) && (o->flags & CFSIM_FLAG_FP64_FINAL))
+        return fail(CFSIM_E_INVALID_ARG, "CFSIM_FLAG_MFMA_BF16 and CFSIM_FLAG_FP64_FINAL exclude each other");
     if (!(o->tie_tol >= 0.0) || !std::isfinite(o->tie_tol))
         return fail(CFSIM_E_INVALID_ARG, "tie_tol must be finite and >= 0");
     return CFSIM_OK;
@@ -111,6 +115,13 @@ double tie_tol_of(const cfsim_options* o, int dtype) {
 }
 
 bool fp64_final(const cfsim_options* o) { return (o->flags & CFSIM_FLAG_FP64_FINAL) != 0; }
+bool mfma_bf16(const cfsim_options* o) { return (o->flags & CFSIM_FLAG_MFMA_BF16) != 0; }
+
+// The BF16 matrix-core variant is an option of cfsim_score_large only.
+cfsim_status check_no_mfma(const cfsim_options* o) {
+    if (mfma_bf16(o)) return fail(CFSIM_E_UNSUPPORTED, "CFSIM_FLAG_MFMA_BF16 applies to cfsim_score_large only");
+    return CFSIM_OK;
+}
 
 // The tiled path (large pairs, resize) has no FP64 pass.
 cfsim_status check_no_fp64_final(const cfsim_options* o) {
@@ -240,7 +251,17 @@ size_t large_ws_bytes(int64_t n_pairs, int max_nodes, int esize, int nslots) {
     return align256((size_t)n_pairs * sizeof(cfsim::LargeState)) + align256((size_t)(n_pairs + 1) * 8) +
            2 * align256(tiles * 8) + align256(tiles * 4) +
            align256((size_t)n_pairs * 2 * max_nodes * cfsim::large_rec_bytes(esize)) +
-           (size_t)n_pairs * nslots * (size_t)global_slot_elems(max_nodes) * (size_t)esize;
+           align256((size_t)n_pairs * nslots * (size_t)global_slot_elems(max_nodes) * (size_t)esize);
+}
+
+// MFMA variant, after the tiled-path workspace: block lists [n_pairs][2][idx
+// stride] | stored blocks [n_pairs][2][cap][2] | BF16 blocks [n_pairs][3][nb^2]
+// (2 KiB per 32 x 32 block).
+size_t mfma_ws_bytes(int64_t n_pairs, int max_nodes) {
+    const size_t nb = (size_t)(max_nodes + 31) / 32;
+    return align256((size_t)n_pairs * 2 * (size_t)cfsim::mfma_idx_stride(max_nodes) * 4) +
+           align256((size_t)n_pairs * 2 * (size_t)cfsim::mfma_block_cap(max_nodes) * 2 * 2048) +
+           align256((size_t)n_pairs * 3 * nb * nb * 2048);
 }
 
 // Options, outputs and workspace of a tiled-path launch (pairs filled by the caller).
@@ -275,6 +296,19 @@ cfsim::LargeJob large_job(const cfsim_options* opt, int64_t n_pairs, int max_nod
     J.bufs = p;
     J.nslots = large_nslots(opt);
     J.slot_elems = global_slot_elems(max_nodes);
+    p += align256((size_t)n_pairs * J.nslots * (size_t)J.slot_elems * (size_t)esize_of(opt->dtype));
+    if (mfma_bf16(opt)) {
+        const size_t nb = (size_t)(max_nodes + 31) / 32;
+        J.mfma = 1;
+        J.mf_nb = (int)nb;
+        J.mf_cap = cfsim::mfma_block_cap(max_nodes);
+        J.mf_idx_stride = cfsim::mfma_idx_stride(max_nodes);
+        J.mf_idx = reinterpret_cast<int*>(p);
+        p += align256((size_t)n_pairs * 2 * (size_t)J.mf_idx_stride * 4);
+        J.mf_tiles = reinterpret_cast<uint4*>(p);
+        p += align256((size_t)n_pairs * 2 * (size_t)J.mf_cap * 2 * 2048);
+        J.mf_blocks = reinterpret_cast<uint4*>(p);
+    }
     return J;
 }
 
@@ -521,6 +555,7 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     if ((s = check_graph(A, "A")) != CFSIM_OK) return s;
     if ((s = check_graph(B, "B")) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if ((s = check_no_mfma(opt)) != CFSIM_OK) return s;
     if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
     const int esize = esize_of(opt->dtype);
     if (opt->resize == CFSIM_RESIZE_BILINEAR) {
@@ -726,6 +761,7 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if ((s = check_no_mfma(opt)) != CFSIM_OK) return s;
     if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
     if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
     if (n_pairs > 0 && (!pair_a || !pair_b || !res))
@@ -770,6 +806,7 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if ((s = check_no_mfma(opt)) != CFSIM_OK) return s;
     if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
     if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
     if (n_pairs > 0 && (!pair_a || !pair_b || !bucket))
@@ -828,7 +865,9 @@ size_t cfsim_large_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
                                   const cfsim_options* opt) {
     (void)ctx;
     if (n_pairs < 1 || !set || !opt || set->max_nodes < 1 || set->max_nodes > cfsim::kLargeMaxNodes) return 0;
-    return large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype), large_nslots(opt));
+    size_t b = large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype), large_nslots(opt));
+    if (mfma_bf16(opt)) b += mfma_ws_bytes(n_pairs, set->max_nodes);
+    return b;
 }
 
 cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -879,6 +918,7 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
+    if ((s = check_no_mfma(opt)) != CFSIM_OK) return s;
     if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
     if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 pairs in one call");
     if (checkpoint_every < 1) return fail(CFSIM_E_INVALID_ARG, "checkpoint_every must be >= 1");

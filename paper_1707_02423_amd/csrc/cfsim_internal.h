@@ -285,9 +285,29 @@ struct LargeJob {
     int nslots;
     long long slot_elems;
     void* recs;          // [n_pairs][2][max_nodes] node records: rows of the row graph, columns of the column graph
+    // BF16 MFMA tile products (CFSIM_FLAG_MFMA_BF16; plain FP32 pairs only)
+    int mfma;
+    int mf_nb, mf_cap;   // 32-node blocks per side of the largest graph; stored blocks per graph
+    long long mf_idx_stride;
+    int* mf_idx;         // [n_pairs][2][mf_idx_stride] block lists of the row graph (0) and column graph (1)
+    uint4* mf_tiles;     // [n_pairs][2][mf_cap][2][128] nonzero 32 x 32 blocks, row-major and transposed
+    uint4* mf_blocks;    // [n_pairs][3][mf_nb^2][128] Y_{k-1}, T1^T, T2^T as BF16 blocks
 };
 
 constexpr int kLargeMaxNodes = 8192;  // bound of the finish kernel's LDS matching state
+constexpr int kMfmaMaxBlocks = kLargeMaxNodes / 32;  // 32-node blocks of the largest graph
+// Stored 32 x 32 blocks per graph on the MFMA variant: all of them, at most
+// twice the node count (a graph of out-degree <= 2 never has more).
+__host__ __device__ inline int mfma_block_cap(int max_nodes) {
+    const long long nb = (max_nodes + 31) / 32;
+    const long long all = nb * nb, two_n = 2ll * max_nodes;
+    return (int)(all < two_n ? all : two_n);
+}
+__host__ __device__ inline long long mfma_idx_stride(int max_nodes) {
+    return 2ll * ((max_nodes + 31) / 32 + 1) + 3ll * mfma_block_cap(max_nodes);
+}
+int launch_mfma_prep(const LargeJob& job, hipStream_t stream);
+int launch_mfma_update(const LargeJob& job, int k, int grid, hipStream_t stream);
 // Bytes of one node record of the tiled path (first 2 successors, 3 predecessors).
 __host__ __device__ inline size_t large_rec_bytes(int esize) { return esize == 8 ? 80 : 48; }
 __host__ __device__ inline long long large_tiles(int n) { return (long long)((n + 127) / 128) * ((n + 63) / 64); }

@@ -29,21 +29,19 @@
 // U_0 = 1/M (every row of R sums to 1).  Each update is then three launches:
 // large_step (U), large_gram (V and the norm partials), large_reduce.
 #include "cfsim_internal.h"
+#include "large_tiles.h"
 #include "pair_device.h"
 
 namespace cfsim {
 
 namespace {
 
+using namespace tiled;
 using dev::better;
 using dev::uni;
 using dev::wave_argmax;
 using dev::wave_sum;
 
-constexpr int kTileRows = 128;                  // rows per tile
-constexpr int kStepThreads = 256;               // 4 waves, 32 rows each
-constexpr int kNWStep = kStepThreads / kWave;
-constexpr int kRowsPerWave = kTileRows / kNWStep;
 constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
 constexpr int kFinishThreads = 1024;
 constexpr int kCache = 8;  // cached partners per line in the matching
@@ -52,15 +50,6 @@ constexpr int kLP = 3;                          // predecessors per lane column 
 constexpr int kSlotU = 0;                       // resize: U_k in slot k % 4
 constexpr int kSlotV = 4;                       // resize: V
 constexpr int kSlotS = 5;                       // resize: expanded final S
-
-__device__ inline int tiles_of(int nC, int nR) { return ((nR + kTileRows - 1) / kTileRows) * ((nC + 63) / 64); }
-static_assert(kTileRows == 128, "large_tiles() in cfsim_internal.h assumes 128-row tiles");
-
-// Pair p's buffer b of slot_elems elements.
-template <typename T>
-__device__ inline T* buf_of(const LargeJob& J, int p, int b) {
-    return reinterpret_cast<T*>(J.bufs) + ((long long)p * J.nslots + b) * J.slot_elems;
-}
 
 // First successors / predecessors of one node with their weights, the list
 // lengths (which may exceed the slots), zero-weight padding.
@@ -99,7 +88,6 @@ __device__ inline NodeRec<T> make_rec(const GraphRef& G, int v) {
     return r;
 }
 
-__device__ inline int pair_of_tile(const LargeJob& J, long long t) { return J.tile_pair[t]; }
 
 __device__ inline bool pair_graphs(const LargeJob& J, int p, GraphRef* A, GraphRef* B) {
     if (J.single) {
@@ -264,57 +252,6 @@ __global__ __launch_bounds__(256) void large_tile_map(LargeJob J) {
     }
 }
 
-// ---------------------------------------------------------------- tiles
-struct Tile {
-    int r0, c0;
-};
-
-// XCD-aware tile order: workgroups are dealt to the 8 XCDs round-robin, so
-// the workgroups of one XCD take one contiguous range of tiles (neighbouring
-// row strips of one pair share rows of the iterate through that XCD's L2).
-struct TileRange {
-    long long first, end, stride;
-};
-__device__ inline TileRange tile_range(const LargeJob& J) {
-    const long long total = J.tile_off[J.n_pairs];
-    const int xcd = blockIdx.x & 7, y = blockIdx.x >> 3;
-    TileRange r;
-    r.first = total * xcd / 8 + y;
-    r.end = total * (xcd + 1) / 8;
-    r.stride = gridDim.x >> 3;
-    return r;
-}
-
-__device__ inline Tile tile_at(const LargeJob& J, long long t, const LargeState* s, int p) {
-    Tile x;
-    const int lt = (int)(t - J.tile_off[p]);
-    const int nct = (s->nC + 63) / 64;
-    x.r0 = (lt / nct) * kTileRows;
-    x.c0 = (lt % nct) * 64;
-    return x;
-}
-
-// Per-tile partials (fixed order: waves, then lanes).
-__device__ void tile_partials(const LargeJob& J, long long t, double nu2, double d2, double* red) {
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    nu2 = wave_sum(nu2);
-    d2 = wave_sum(d2);
-    if (lane == 0) {
-        red[wave] = nu2;
-        red[kNWStep + wave] = d2;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double a = 0.0, b = 0.0;
-        for (int w = 0; w < kNWStep; ++w) {
-            a += red[w];
-            b += red[kNWStep + w];
-        }
-        J.part_nu[t] = a;
-        J.part_delta[t] = b;
-    }
-    __syncthreads();
-}
 
 // After update launch k: one workgroup per active pair sums its tiles'
 // partials in tile order and decides whether the pair stops.  compute: a new
@@ -1010,6 +947,17 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
     if ((e = (int)hipGetLastError()) != 0) return e;
     hipLaunchKernelGGL(large_tile_map, dim3(J.n_pairs < 4096 ? J.n_pairs : 4096), dim3(256), 0, stream, J);
     if ((e = (int)hipGetLastError()) != 0) return e;
+    if (J.mfma) {  // BF16 matrix-core products (plain FP32 pairs)
+        if ((e = launch_mfma_prep(J, stream)) != 0) return e;
+        for (int k = 1; k <= J.max_iter + 1; ++k) {
+            if ((e = launch_mfma_update(J, k, grid, stream)) != 0) return e;
+            hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
+            if ((e = (int)hipGetLastError()) != 0) return e;
+        }
+        const size_t lds = large_finish_lds(J.max_nodes);
+        hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
+        return (int)hipGetLastError();
+    }
     if (J.resize) {
         hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, 0);
         if ((e = (int)hipGetLastError()) != 0) return e;
