@@ -311,7 +311,34 @@ def workload_legs(ctx, stream, reps=3):
                               matchings_equal_fp32_fp64=int(sum(np.array_equal(x, y) for x, y in
                                                                 zip(b32.matches(), b64.matches()))),
                               **errs)
-    del b, b32, b64, gs
+    # the same call with block-sparse BF16 matrix-core products (FP32 sums)
+    bm = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, want_S=True, path="large",
+                  mfma=True)
+    bm.run()
+    torch.cuda.synchronize()
+    ms_m = _time_ms(bm.run, reps, stream)
+    rm = bm.results()
+    errs_m = err_summary(*seg_errors(bm.S, b64.S, bm.nA * bm.nB))
+    # executed matrix-core work per update of a pair: stage 1 takes every
+    # nonzero 32 x 32 block of A twice (A S^T, A^T S^T) per block row of S,
+    # stage 2 every nonzero block of B twice per block column; two 32x32x16
+    # MFMAs (32,768 flops each) per block product
+    def nblocks(g):
+        return len(set(zip((np.asarray(g.src) // 32).tolist(), (np.asarray(g.dst) // 32).tolist())))
+    gr = w["graphs"]
+    ex = 0.0
+    for p in range(len(w["pair_a"])):
+        ga, gb = gr[w["pair_a"][p]], gr[w["pair_b"][p]]
+        nRb, nCb = (gb.n + 31) // 32, (ga.n + 31) // 32
+        ex += float(rm["iters"][p]) * (nRb * 2 * nblocks(ga) + nCb * 2 * nblocks(gb)) * 2 * 32768.0
+    out["large_pairs"]["mfma_bf16"] = dict(
+        ms_per_call=ms_m, pairs_per_s=len(rm) / (ms_m * 1e-3), speedup_over_fp32=ms / ms_m,
+        mfma_roofline=dict(bound="mfma", executed_tflops=ex / 1e12, achieved=ex / (ms_m * 1e-3) / 1e12,
+                           peak=2500.0, unit="TFLOP/s", frac=ex / (ms_m * 1e-3) / 2.5e15),
+        status_counts={int(k): int(v) for k, v in zip(*np.unique(rm["status"], return_counts=True))},
+        matchings_equal_fp64=int(sum(np.array_equal(x, y) for x, y in zip(bm.matches(), b64.matches()))),
+        **errs_m)
+    del b, b32, b64, bm, gs
 
     # a8 + a11: a 200-node query against 65,536 power-law graphs, then top-16
     w = config_graphs(4)
@@ -397,9 +424,9 @@ def profile_only(spec: str):
     """Launch drivers for profilers; inputs as in the bench, results unchecked:
       pair:NA:NB:DTYPE:MAX_ITER:REPS  the plain path on one seeded pair
                                       (tol 0: every launch runs MAX_ITER updates)
-      workload:NAME:REPS              NAME = batch, large, resize, query,
-                                      backward or fp64final; FP32, REPS calls
-                                      after one warm-up"""
+      workload:NAME:REPS              NAME = batch, large, largemfma, resize,
+                                      query, backward or fp64final; FP32, REPS
+                                      calls after one warm-up"""
     import torch
     from paper_1707_02423_amd import cfsim as cfm
     from cfgsynth import Grammar, config_graphs, make_cfg
@@ -414,11 +441,13 @@ def profile_only(spec: str):
             cfm.score(ctx, gs, 0, 1, dtype=dt, max_iter=K, tol=0.0, want_S=False, sync=False)
     elif f[0] == "workload" and len(f) == 3:
         name, reps = f[1], int(f[2])
-        idx = {"batch": 1, "resize": 1, "fp64final": 1, "large": 2, "backward": 3, "query": 4}.get(name)
+        idx = {"batch": 1, "resize": 1, "fp64final": 1, "large": 2, "largemfma": 2, "backward": 3,
+               "query": 4}.get(name)
         if idx is None:
             raise SystemExit(f"unknown workload {name!r}")
         w = config_graphs(idx)
-        kw = dict(path="large") if name == "large" else {}
+        kw = dict(path="large") if name in ("large", "largemfma") else {}
+        kw.update(dict(mfma=True) if name == "largemfma" else {})
         kw.update(dict(resize="bilinear") if name == "resize" else {})
         kw.update(dict(fp64_final=True) if name == "fp64final" else {})
         gs = cfm.pack(ctx, w["graphs"])
