@@ -475,6 +475,7 @@ def main():
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=3, help="timed eager passes for per-kernel durations")
     ap.add_argument("--no-legs", action="store_true", help="skip the other workloads (large pairs, query, ...)")
+    ap.add_argument("--no-tune", action="store_true", help="time the default plan (no autotuning)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device copy of this size first (profiler byte-counter calibration)")
     ap.add_argument("--only", default="", help="profiling driver instead of the bench (see profile_only)")
@@ -504,6 +505,13 @@ def main():
     ctx = cf.Context(0)
     gs = cf.pack(ctx, graphs)
     torch.cuda.synchronize()
+
+    # ---------------------------------------------------------------- plan autotuning (untimed)
+    tune_rec = None
+    if not args.no_tune:
+        from paper_1707_02423_amd import tune
+        tune_rec = tune.autotune(ctx, gs, pa, pb, "f32", reps=3)
+        tune.save(tune_rec)
 
     # ---------------------------------------------------------------- batched
     batch = cf.Batch(ctx, gs, pa, pb, dtype="f32", want_match=True, want_S=False)
@@ -625,7 +633,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "all-pairs batch: 256 synthetic CFGs, n ~ U[8,128], loop trips log-uniform "
                                "[1,1e4], 32,640 pairs, FP32 with FP64 reductions, tol 1e-12, max 200 iterations, "
-                               "one HIP-graph replay of the persistent bucketed launch",
+                               "one HIP-graph replay of the persistent bucketed launch (autotuned plan)",
                    "pairs": n_pairs, "graphs": len(graphs), "seed": int(w["seed"])},
         "roofline": {"bound": "alu", "achieved": dom_achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": dom_achieved / FP32_VECTOR_PEAK,
@@ -638,6 +646,10 @@ def main():
                          "frac": lds_bytes / (ms * 1e-3) / LDS_PEAK},
         "algorithmic_flops_per_step": flops,
     }
+    if tune_rec is not None:
+        line["plan_tuning"] = dict(table={str(c): v for c, v in enumerate(tune_rec["table"]) if v >= 0},
+                                   default_ms_per_pass=tune_rec["base_ms"], tuned_ms_per_pass=tune_rec["tuned_ms"],
+                                   classes_tried=len(tune_rec["classes"]))
     line.update(plain)
     line.update(ver)
     if not args.no_legs:

@@ -317,6 +317,28 @@ cfsim_status cfsim_context_set_timing(cfsim_context* ctx, int32_t on);
 cfsim_status cfsim_batch_timings(cfsim_context* ctx, float* ms);
 
 /*
+ * Batch plan tuning (step a8).  The batched path runs each pair on the first
+ * LDS kernel (bucket 0..4, in increasing size) that holds it.  A tune table
+ * of CFSIM_TUNE_CLASSES entries per arithmetic type may send the pairs of a
+ * class to a larger LDS kernel; classes group pairs by half octaves of
+ * n_A * n_B (cfsim_tune_class; class c holds 2 log2(n_A n_B) in [c, c+1),
+ * the last class everything above).  Entry -1 keeps the first kernel that
+ * holds the pair; an entry b in 0..4 is used when b is larger than that
+ * kernel and b holds the pair.  The table is a host array; it is copied into
+ * the context and every later cfsim_score_batch / cfsim_batch_buckets call
+ * of that dtype plans with it (a changed table invalidates the cached launch
+ * graph).  cfsim_context_set_tune with table NULL restores the default.
+ * Tables are produced by the autotuner of the Python package, which times
+ * every candidate kernel per class with HIP events and caches the fastest.
+ * Errors: CFSIM_E_INVALID_ARG for a NULL context, a bad dtype, n other than
+ * CFSIM_TUNE_CLASSES or an entry outside -1..4.
+ */
+#define CFSIM_TUNE_CLASSES 32
+int32_t cfsim_tune_class(int32_t n_a, int32_t n_b);
+cfsim_status cfsim_context_set_tune(cfsim_context* ctx, int32_t dtype, const int32_t* table, int32_t n);
+cfsim_status cfsim_context_get_tune(const cfsim_context* ctx, int32_t dtype, int32_t* table, int32_t n);
+
+/*
  * Step a10 - reverse mode: d(sum_p grad_score[p] * score_p) / d(w), added to
  * grad_w[total_edges] (device, FP64, CSR order of `set`; not cleared).  The
  * matching and the update count of each pair are held fixed (the

@@ -25,6 +25,7 @@ FLAG_MFMA_BF16 = 2
 NUM_BUCKETS = 7  # batch buckets: 0-4 LDS kernels, 5 global-memory kernel, 6 invalid pairs
 PACK_BAD_INDEX, PACK_NONFINITE, PACK_NEGATIVE = 1, 2, 4
 NOALLOC_SCRATCH_BYTES = 16 << 20  # CFSIM_NOALLOC_SCRATCH_BYTES
+TUNE_CLASSES = 32  # CFSIM_TUNE_CLASSES
 
 STATUS_NAMES = {0: "CFSIM_OK", -1: "CFSIM_E_INVALID_ARG", -2: "CFSIM_E_BAD_GRAPH", -3: "CFSIM_E_NONFINITE",
                 -4: "CFSIM_E_NEGWEIGHT", -5: "CFSIM_E_WORKSPACE", -6: "CFSIM_E_UNSUPPORTED", -7: "CFSIM_E_HIP"}
@@ -94,6 +95,9 @@ SIGNATURES = {
     "cfsim_bucket_kernel": (ctypes.c_char_p, [_I32, _I32]),
     "cfsim_context_set_timing": (ctypes.c_int, [_P, _I32]),
     "cfsim_batch_timings": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "cfsim_tune_class": (_I32, [_I32, _I32]),
+    "cfsim_context_set_tune": (ctypes.c_int, [_P, _I32, _P, _I32]),
+    "cfsim_context_get_tune": (ctypes.c_int, [_P, _I32, _P, _I32]),
     "cfsim_topk_workspace_size": (_SZ, [_I64, _I32]),
     "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
 }
@@ -150,6 +154,21 @@ class Context:
     def set_timing(self, on: bool):
         """Eager batched launches with an event pair around each bucket kernel."""
         _check(lib().cfsim_context_set_timing(self.handle, 1 if on else 0))
+
+    def set_tune(self, dtype: str, table):
+        """Batch plan tune table of `dtype` (TUNE_CLASSES entries, -1 = default; None resets)."""
+        d = {"f64": F64, "f32": F32}[dtype]
+        if table is None:
+            _check(lib().cfsim_context_set_tune(self.handle, d, None, TUNE_CLASSES))
+            return
+        arr = (ctypes.c_int32 * TUNE_CLASSES)(*[int(x) for x in table])
+        _check(lib().cfsim_context_set_tune(self.handle, d, arr, TUNE_CLASSES))
+
+    def get_tune(self, dtype: str) -> list:
+        d = {"f64": F64, "f32": F32}[dtype]
+        arr = (ctypes.c_int32 * TUNE_CLASSES)()
+        _check(lib().cfsim_context_get_tune(self.handle, d, arr, TUNE_CLASSES))
+        return list(arr)
 
     def batch_timings(self) -> np.ndarray:
         """Milliseconds of each bucket kernel of the last timed batch call (waits for it)."""

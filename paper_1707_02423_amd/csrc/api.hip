@@ -35,6 +35,7 @@ struct cfsim_context {
     hipEvent_t t0[cfsim::kBuckets] = {};
     hipEvent_t t1[cfsim::kBuckets] = {};
     void* scratch = nullptr;                // this device's copy of `scratch`
+    int8_t tune[2][cfsim::kTuneClasses];    // batch plan: LDS variant per tune class, [F64, F32]
 };
 
 namespace {
@@ -357,11 +358,13 @@ bool graphs_disabled() {
     return nog && nog[0] == '1';
 }
 
-std::vector<unsigned char> set_call_key(const cfsim_graph_set* set, const int32_t* pair_a, const int32_t* pair_b,
+std::vector<unsigned char> set_call_key(const cfsim_context* ctx, const cfsim_graph_set* set,
+                                        const int32_t* pair_a, const int32_t* pair_b,
                                         int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
                                         int32_t* match, const int64_t* match_off, void* S_out,
                                         const int64_t* S_off, void* ws) {
     std::vector<unsigned char> key;
+    append_key(key, ctx->tune);
     append_key(key, *set);
     append_key(key, pair_a);
     append_key(key, pair_b);
@@ -403,6 +406,7 @@ cfsim_status cfsim_context_create(cfsim_context** out, int device) {
     if ((e = (int)hipSetDevice(device)) != 0) return hip_fail(e, "hipSetDevice");
     cfsim_context* ctx = new cfsim_context();
     ctx->device = device;
+    memset(ctx->tune, -1, sizeof(ctx->tune));
     if ((e = (int)hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device)) != 0) {
         delete ctx;
         return hip_fail(e, "hipDeviceGetAttribute");
@@ -667,6 +671,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     plan.order = b.order;
     plan.bounds = b.bounds;
     plan.queues = b.queues;
+    memcpy(plan.tune, ctx->tune[dtype_index(dtype)], sizeof(plan.tune));
     int e = cfsim::launch_plan(plan, st);
     if (e != 0) return e;
     cfsim::PairJob job{};
@@ -748,7 +753,7 @@ static cfsim_status run_large(cfsim_context* ctx, const cfsim_graph_set* set, co
         if (e != 0) return hip_fail(e, "tiled-path launch");
         return ok();
     }
-    const auto key = set_call_key(set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    const auto key = set_call_key(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
     return replay_or_capture(ctx, &ctx->large_graph, &ctx->large_exec, &ctx->large_key, key, st, [&](hipStream_t cs) {
         return enqueue_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs);
     });
@@ -793,7 +798,7 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
         if (ctx->timing) ctx->timed = 1;
         return ok();
     }
-    const auto key = set_call_key(set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    const auto key = set_call_key(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
     return replay_or_capture(ctx, &ctx->graph, &ctx->exec, &ctx->key, key, st, [&](hipStream_t cs) {
         return enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs,
                              false);
@@ -820,6 +825,7 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     if (e != 0) return hip_fail(e, "hipSetDevice");
     cfsim::PlanJob plan{};
     plan.set = ref_of(set);
+    memcpy(plan.tune, ctx->tune[dtype_index(opt->dtype)], sizeof(plan.tune));
     plan.pair_a = pair_a;
     plan.pair_b = pair_b;
     plan.n_pairs = n_pairs;
@@ -827,6 +833,32 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     plan.slot_elems = global_slot_elems(set->max_nodes);
     e = cfsim::launch_buckets(plan, bucket, static_cast<hipStream_t>(stream));
     if (e != 0) return hip_fail(e, "bucket launch");
+    return ok();
+}
+
+int32_t cfsim_tune_class(int32_t n_a, int32_t n_b) { return cfsim::tune_class(n_a, n_b); }
+
+cfsim_status cfsim_context_set_tune(cfsim_context* ctx, int32_t dtype, const int32_t* table, int32_t n) {
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (dtype != CFSIM_F64 && dtype != CFSIM_F32) return fail(CFSIM_E_INVALID_ARG, "dtype must be CFSIM_F64 or CFSIM_F32");
+    if (n != cfsim::kTuneClasses) return fail(CFSIM_E_INVALID_ARG, "table needs %d entries (got %d)", cfsim::kTuneClasses, n);
+    if (!table) {
+        memset(ctx->tune[dtype_index(dtype)], -1, cfsim::kTuneClasses);
+        return ok();
+    }
+    for (int c = 0; c < n; ++c)
+        if (table[c] < -1 || table[c] >= cfsim::kNumVariants)
+            return fail(CFSIM_E_INVALID_ARG, "table[%d] = %d: must be -1 or an LDS bucket 0..%d", c, table[c],
+                        cfsim::kNumVariants - 1);
+    for (int c = 0; c < n; ++c) ctx->tune[dtype_index(dtype)][c] = (int8_t)table[c];
+    return ok();
+}
+
+cfsim_status cfsim_context_get_tune(const cfsim_context* ctx, int32_t dtype, int32_t* table, int32_t n) {
+    if (!ctx || !table) return fail(CFSIM_E_INVALID_ARG, "context or table is NULL");
+    if (dtype != CFSIM_F64 && dtype != CFSIM_F32) return fail(CFSIM_E_INVALID_ARG, "dtype must be CFSIM_F64 or CFSIM_F32");
+    if (n != cfsim::kTuneClasses) return fail(CFSIM_E_INVALID_ARG, "table needs %d entries (got %d)", cfsim::kTuneClasses, n);
+    for (int c = 0; c < n; ++c) table[c] = ctx->tune[dtype_index(dtype)][c];
     return ok();
 }
 

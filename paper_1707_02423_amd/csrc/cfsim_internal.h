@@ -198,6 +198,16 @@ constexpr int kBucketGlobal = kNumVariants;
 constexpr int kBucketInvalid = kNumVariants + 1;
 constexpr int kBuckets = kNumVariants + 2;
 static_assert(kBuckets == CFSIM_NUM_BUCKETS, "bucket count of the C ABI");
+// Tune classes of the batch plan: pairs grouped by 2 log2(n_A n_B) (half
+// octaves of S's entry count); a tuned table may send a class to a larger
+// LDS variant than the first one that holds it.
+constexpr int kTuneClasses = CFSIM_TUNE_CLASSES;
+__host__ __device__ inline int tune_class(int nA, int nB) {
+    const double a = (double)(nA > 1 ? nA : 1) * (double)(nB > 1 ? nB : 1);
+    int c = (int)(2.0 * log2(a));
+    return c < 0 ? 0 : (c >= kTuneClasses ? kTuneClasses - 1 : c);
+}
+
 struct PlanJob {
     SetRef set;
     const int32_t* pair_a;
@@ -211,6 +221,8 @@ struct PlanJob {
     int32_t* order;
     int32_t* bounds;
     int32_t* queues;
+    // LDS variant per tune class (-1: the first variant that holds the pair)
+    int8_t tune[kTuneClasses];
 };
 
 // Host-side launchers (return hipError_t as int).

@@ -1001,6 +1001,10 @@ __device__ void classify(const PlanJob& P, int64_t p, int* bucket, int* cls) {
     int b = kBucketInvalid;
     for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
         if (choose_shape(nA, nB, mA, mB, v, P.esize, &sh)) b = v;
+    if (b < kNumVariants) {  // a tuned larger variant for the pair's class, if it holds the pair
+        const int t = P.tune[tune_class(nA, nB)];
+        if (t > b && t < kNumVariants && choose_shape(nA, nB, mA, mB, t, P.esize, &sh)) b = t;
+    }
     if (b == kBucketInvalid && global_fits(nA, nB, mA, mB, P.esize, P.slot_elems, &sh)) b = kBucketGlobal;
     if (P.filter && b == kBucketInvalid) {  // no FP64 kernel holds it: the FP32 result stays
         *bucket = -1;

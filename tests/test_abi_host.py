@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1707_02423_amd import cfsim as cf
@@ -351,3 +352,18 @@ def test_score_noalloc_validation():
     got = L.cfsim_score_noalloc(ctypes.c_void_p(0x1000), ctypes.byref(big_a), ctypes.byref(big_b),
                                 ctypes.byref(opt), None, None, 0x1000, None)
     assert got == -6 and "static scratch" in L.cfsim_last_error().decode()
+
+
+def test_tune_class_and_table_validation():
+    """Tune classes are half octaves of n_A * n_B; the table calls check
+    their arguments on the host."""
+    L = cf.lib()
+    assert L.cfsim_tune_class(1, 1) == 0
+    assert L.cfsim_tune_class(8, 16) == 14
+    assert L.cfsim_tune_class(128, 128) == 28
+    assert L.cfsim_tune_class(100, 7) == int(2 * np.log2(700))
+    assert L.cfsim_tune_class(60000, 60000) == cf.TUNE_CLASSES - 1
+    arr = (ctypes.c_int32 * cf.TUNE_CLASSES)(*([-1] * cf.TUNE_CLASSES))
+    assert L.cfsim_context_set_tune(None, cf.F32, arr, cf.TUNE_CLASSES) == -1
+    assert "context" in L.cfsim_last_error().decode()
+    assert L.cfsim_context_get_tune(None, cf.F32, arr, cf.TUNE_CLASSES) == -1
