@@ -25,6 +25,7 @@ using namespace dev;
 
 constexpr int kBwdThreads = 512;
 constexpr int kBwdLds = 78 * 1024;
+constexpr int kAChunks = 8;  // A edges held by the lanes (64 per chunk) in the lane-parallel edge sums
 
 template <typename T>
 __device__ inline T* slot_buf(T* base, long long slot_elems, int b) {
@@ -119,6 +120,8 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
     double* gB = gA + A.nnz;
     int* srcA = reinterpret_cast<int*>(smem + lists_bytes + align16((size_t)(A.nnz + B.nnz) * 8));
     int* srcB = srcA + A.nnz;
+    const size_t scratch_off = lists_bytes + align16((size_t)(A.nnz + B.nnz) * 8) + align16((size_t)(A.nnz + B.nnz) * 4);
+    const size_t scratch_bytes = (size_t)NW * kAChunks * kWave * sizeof(T);
 
     // workspace slot: checkpoints | segment (ckpt+1) | Ybar | Gbar | nu[max_iter]
     T* base = reinterpret_cast<T*>(static_cast<unsigned char*>(J.ws) + (size_t)blockIdx.x * J.slot_bytes);
@@ -162,6 +165,14 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
         }
     }
 
+    // ---- edge sums with lanes over A edges need a per-wave scratch of their
+    // per-step partials (at most kAChunks * 64 A edges; otherwise the
+    // thread-per-edge loops below)
+    const int wave = uni(tid / kWave);
+    const int nchA = (keptA + kWave - 1) / kWave;
+    T* part = reinterpret_cast<T*>(smem + scratch_off);
+    const bool lane_edges = nchA <= kAChunks && scratch_off + scratch_bytes <= (size_t)kBwdLds;
+
     // ---- reverse: Gbar = g * indicator(matching)
     const int64_t mo = J.match_off ? J.match_off[p] : 0;
     for (long long t = tid; t < E; t += NT) Gbar[t] = T(0);
@@ -190,8 +201,53 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
             const T invnu = T(1.0 / nus[k]);
             for (long long t = tid; t < E; t += NT) Ybar[t] = (Gbar[t] - a * Sk1[t]) * invnu;
             __syncthreads();
-            // edge gradients (A edges, then B edges): shared summand
-            for (int e = tid; e < keptA; e += NT) {
+            // edge gradients: every pair of a B edge f = (i -> u) and an A edge
+            // e = (p -> q) has the summand c = Ybar[i][p] S[u][q] + S[i][p] Ybar[u][q];
+            // dA[e] += w_f c and dB[f] += w_e c
+            if (lane_edges) {
+                // wave w: B edges f = w, w + NW, ...; lane l: A edges e = l + 64 ch;
+                // dB[f] is a wave sum, dA[e] the waves' partials summed in wave order
+                const int lane = tid & (kWave - 1);
+                int ep[kAChunks], eq[kAChunks];
+                T ew[kAChunks], accA[kAChunks];
+#pragma unroll
+                for (int ch = 0; ch < kAChunks; ++ch) {
+                    const int e = ch * kWave + lane;
+                    const bool has = e < keptA;  // absent edges read entry 0 with weight 0
+                    ep[ch] = has ? srcA[e] : 0;
+                    eq[ch] = has ? A.ci[e] : 0;
+                    ew[ch] = has ? T(A.w[e]) : T(0);
+                    accA[ch] = T(0);
+                }
+                for (int f = wave; f < keptB; f += NW) {
+                    const int i = uni(srcB[f]), u = uni(B.ci[f]);
+                    const T wf = T(B.w[f]);
+                    const T* Yi = Ybar + (long long)i * nC;
+                    const T* Yu = Ybar + (long long)u * nC;
+                    const T* Si = Sk + (long long)i * nC;
+                    const T* Su = Sk + (long long)u * nC;
+                    T pb = T(0);
+#pragma unroll
+                    for (int ch = 0; ch < kAChunks; ++ch) {
+                        if (ch < nchA) {
+                            const T c = Yi[ep[ch]] * Su[eq[ch]] + Si[ep[ch]] * Yu[eq[ch]];
+                            accA[ch] = fma_t(wf, c, accA[ch]);
+                            pb = fma_t(ew[ch], c, pb);
+                        }
+                    }
+                    const double sb = wave_sum((double)pb);
+                    if (lane == 0) gB[f] += sb;
+                }
+#pragma unroll
+                for (int ch = 0; ch < kAChunks; ++ch)
+                    if (ch < nchA) part[(wave * kAChunks + ch) * kWave + lane] = accA[ch];
+                __syncthreads();
+                for (int e = tid; e < keptA; e += NT) {
+                    double a = 0.0;
+                    for (int w = 0; w < NW; ++w) a += (double)part[(w * kAChunks + e / kWave) * kWave + (e % kWave)];
+                    gA[e] += a;
+                }
+            } else for (int e = tid; e < keptA; e += NT) {
                 const int pa = srcA[e], qa = A.ci[e];
                 T acc = T(0);
                 for (int f = 0; f < keptB; ++f) {
@@ -202,7 +258,7 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
                 }
                 gA[e] += (double)acc;
             }
-            for (int f = tid; f < keptB; f += NT) {
+            if (!lane_edges) for (int f = tid; f < keptB; f += NT) {
                 const int i = srcB[f], u = B.ci[f];
                 T acc = T(0);
                 for (int e = 0; e < keptA; ++e) {
@@ -213,6 +269,7 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
                 }
                 gB[f] += (double)acc;
             }
+            __syncthreads();  // gB of this step complete; Ybar and Gbar are rewritten next
             // Gbar = M Ybar
             (void)apply_M(Ybar, Gbar, T(1), sh, G, red + (k & 1) * NW);
         }
