@@ -534,13 +534,32 @@ cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_node
 }
 
 // ------------------------------------------------------------------ plain pair (a2-a7)
-// The plain path picks the first LDS variant that holds the pair, else the
-// global-memory kernel; -1 if neither can take it.
+// One pair alone is latency-bound: every update ends in a workgroup barrier,
+// so more waves (fewer rows per wave) shorten it.  The plain path takes the
+// smaller of the 512- and 1024-thread kernels that holds the pair with at
+// most two rows per wave, else the 1024-thread two-chunk kernel if it holds
+// the pair, else the first LDS kernel that does, else the global-memory
+// kernel; -1 if none can take it.  (Measured on one MI355X: a 12 x 16 pair
+// 292 us on the 512-thread kernel against 763 us on the one-wave kernel.)
 static int plain_variant(int nA, int nB, int nnzA, int nnzB, int esize, cfsim::PairShape* sh) {
-    for (int v = 0; v < cfsim::kNumVariants; ++v)
-        if (cfsim::choose_shape(nA, nB, nnzA, nnzB, v, esize, sh)) return v;
-    if (cfsim::global_fits(nA, nB, nnzA, nnzB, esize, (long long)nA * nB, sh)) return cfsim::kBucketGlobal;
-    return -1;
+    int first = -1;
+    for (int v = 0; v < cfsim::kNumVariants && first < 0; ++v)
+        if (cfsim::choose_shape(nA, nB, nnzA, nnzB, v, esize, sh)) first = v;
+    if (first < 0) {
+        if (cfsim::global_fits(nA, nB, nnzA, nnzB, esize, (long long)nA * nB, sh)) return cfsim::kBucketGlobal;
+        return -1;
+    }
+    cfsim::PairShape s;
+    for (int v = first > 2 ? first : 2; v <= 3; ++v)
+        if (cfsim::choose_shape(nA, nB, nnzA, nnzB, v, esize, &s) && cfsim::variant_info(v, esize).nt / 32 >= s.nR) {
+            *sh = s;
+            return v;
+        }
+    if (first <= 3 && cfsim::choose_shape(nA, nB, nnzA, nnzB, 3, esize, &s)) {
+        *sh = s;
+        return 3;
+    }
+    return first;
 }
 
 size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b, const cfsim_options* opt) {

@@ -284,13 +284,18 @@ def test_batch_deterministic_and_graph_replay(cf, ctx):
 
 
 def test_batch_matches_plain_path(cf, ctx):
+    # the plain path may run a pair on a larger kernel than the batch (its
+    # norms then sum over another number of waves): FP64 rounding apart, the
+    # same S, update count and matching
     w = config_graphs(1, scale=6 / 256)
     gs = cf.pack(ctx, w["graphs"])
     res, matches, Ss = cf.score_batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", want_S=True)
     for p in range(len(res)):
         r = cf.score(ctx, gs, int(w["pair_a"][p]), int(w["pair_b"][p]), dtype="f64")
-        assert np.array_equal(r["S"], Ss[p])  # same kernels, same order of arithmetic
-        assert np.array_equal(r["match"], matches[p]) and r["margin"] == res["margin"][p]
+        assert np.max(np.abs(r["S"] - Ss[p])) <= 1e-13 * np.max(Ss[p])
+        assert r["iters"] == res["iters"][p]
+        if not (res["status"][p] & NEAR_TIE):
+            assert np.array_equal(r["match"], matches[p])
 
 
 def test_workload1_full_size_sampled(cf, ctx):
