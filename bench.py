@@ -369,7 +369,7 @@ def workload_legs(ctx, stream, reps=3):
     # a10: 1,024 pairs n ~ U[16,256], forward then reverse mode (checkpoints every 8)
     w = config_graphs(3)
     gs = cf.pack(ctx, w["graphs"])
-    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True)
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, checkpoint_every=8)
     b.run()
     gsc = torch.ones(len(w["pair_a"]), dtype=torch.float64, device=gs.w.device)
     gw = torch.zeros_like(gs.w)
@@ -380,7 +380,7 @@ def workload_legs(ctx, stream, reps=3):
     ms_b = _time_ms(lambda: cf.backward(b, gsc, gw, checkpoint_every=8), reps, stream)
     g32 = torch.zeros_like(gs.w)
     cf.backward(b, gsc, g32, checkpoint_every=8)
-    b64 = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", want_match=True)
+    b64 = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", want_match=True, checkpoint_every=8)
     b64.run()
     g64 = torch.zeros_like(gs.w)
     st64 = cf.backward(b64, gsc, g64, checkpoint_every=8)
@@ -391,7 +391,8 @@ def workload_legs(ctx, stream, reps=3):
                            for g in (int(w["pair_a"][p]), int(w["pair_b"][p]))])
     e = torch.as_tensor(eidx, device=gs.w.device)
     gerr = float(torch.linalg.norm(g32[e] - g64[e]) / torch.linalg.norm(g64[e]))
-    out["backward"] = dict(workload="1,024 pairs n ~ U[16,256], FP32, gradient w.r.t. every edge weight",
+    out["backward"] = dict(workload="1,024 pairs n ~ U[16,256], FP32, gradient w.r.t. every edge weight, "
+                                    "forward with checkpoints every 8 updates",
                            forward_ms=ms_f, backward_ms=ms_b,
                            pairs_per_s_fwd_bwd=len(w["pair_a"]) / ((ms_f + ms_b) * 1e-3),
                            backward_over_forward=ms_b / ms_f, pairs_skipped=int(torch.count_nonzero(st)),

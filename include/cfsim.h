@@ -344,7 +344,11 @@ cfsim_status cfsim_context_get_tune(const cfsim_context* ctx, int32_t dtype, int
  * matching and the update count of each pair are held fixed (the
  * almost-everywhere derivative): fwd[p].iters and match (at match_off[p])
  * must come from the forward call with the same set, pairs and options.
- * The forward is recomputed with S stored every checkpoint_every updates.
+ * The reverse walks segments of checkpoint_every updates backwards, each
+ * recomputed from its first iterate: S_0, or the forward's checkpoints when
+ * ckpt / ckpt_off are given (from cfsim_score_batch_ckpt with the same
+ * checkpoint_every; both NULL: the forward is recomputed here first, S stored
+ * every checkpoint_every updates).
  * Degenerate pairs contribute zero.  pair_status[n_pairs] (device, may be
  * NULL) receives 0, or CFSIM_INVALID_INPUT for a pair that was skipped (bad
  * ids, or lists too long for the kernel).  Graphs shared between pairs
@@ -357,7 +361,29 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
                                   const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
                                   const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
                                   const double* grad_score, double* grad_w, int32_t* pair_status,
-                                  int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream);
+                                  int32_t checkpoint_every, const void* ckpt, const int64_t* ckpt_off,
+                                  void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * cfsim_score_batch that also leaves the forward checkpoints the reverse
+ * mode starts its segments from (so cfsim_score_backward need not recompute
+ * the forward): pair p's S_k for k = c * checkpoint_every, c = 1, 2, ...,
+ * k < the pair's update count, at ckpt + ckpt_off[p] + (c - 1) n_A n_B
+ * elements of opt->dtype, n_B x n_A row-major.  The caller sizes pair p's
+ * area as (max_iter / checkpoint_every) n_A n_B elements (device memory,
+ * owned by the caller; entries past the update count are not written).
+ * Pass the same ckpt, ckpt_off and checkpoint_every to cfsim_score_backward.
+ * Same arguments and results as cfsim_score_batch otherwise.  Errors as
+ * cfsim_score_batch, plus CFSIM_E_INVALID_ARG for checkpoint_every < 1 or a
+ * NULL ckpt / ckpt_off, CFSIM_E_UNSUPPORTED with resize or
+ * CFSIM_FLAG_FP64_FINAL.
+ */
+cfsim_status cfsim_score_batch_ckpt(cfsim_context* ctx, const cfsim_graph_set* set,
+                                    const int32_t* pair_a, const int32_t* pair_b, int64_t n_pairs,
+                                    const cfsim_options* opt, cfsim_pair_result* res,
+                                    int32_t* match, const int64_t* match_off,
+                                    void* S_out, const int64_t* S_off, void* ckpt, const int64_t* ckpt_off,
+                                    int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Step a11 - ranking of a query against a database: the k best scores.

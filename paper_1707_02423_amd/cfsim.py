@@ -85,8 +85,11 @@ SIGNATURES = {
     "cfsim_score_batch": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
                                          _P, _P, _P, _P, _P, _SZ, _P]),
     "cfsim_backward_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options), _I32]),
+    "cfsim_score_batch_ckpt": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64,
+                                              ctypes.POINTER(Options), _P, _P, _P, _P, _P, _P, _P, _I32, _P, _SZ,
+                                              _P]),
     "cfsim_score_backward": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
-                                            _P, _P, _P, _P, _P, _P, _I32, _P, _SZ, _P]),
+                                            _P, _P, _P, _P, _P, _P, _I32, _P, _P, _P, _SZ, _P]),
     "cfsim_large_workspace_size": (_SZ, [_P, ctypes.POINTER(GraphSetC), _I64, ctypes.POINTER(Options)]),
     "cfsim_score_large": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options), _P,
                                          _P, _P, _P, _P, _P, _SZ, _P]),
@@ -339,7 +342,7 @@ class Batch:
 
     def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
                  resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch",
-                 tie_tol=0.0, fp64_final=False, mfma=False):
+                 tie_tol=0.0, fp64_final=False, mfma=False, checkpoint_every=0):
         if path not in ("batch", "large"):
             raise ValueError("path must be 'batch' (cfsim_score_batch) or 'large' (cfsim_score_large)")
         self.path = path
@@ -373,6 +376,17 @@ class Batch:
             self.S_off_h = off[:-1]
             self.S_off = torch.as_tensor(self.S_off_h).to(dev)
             self.S = torch.empty(max(int(off[-1]), 1), dtype=_torch_dtype(self.opt), device=dev)
+        # forward checkpoints for the reverse mode: S_k every checkpoint_every
+        # updates (max_iter // checkpoint_every iterates of n_A n_B per pair)
+        self.checkpoint_every = int(checkpoint_every)
+        self.ckpt = self.ckpt_off = None
+        if self.checkpoint_every > 0:
+            if path != "batch":
+                raise ValueError("forward checkpoints are taken on the batched path")
+            per = (int(max_iter) // self.checkpoint_every) * nA * nB
+            off = np.concatenate([[0], np.cumsum(per)]).astype(np.int64)
+            self.ckpt_off = torch.as_tensor(off[:-1]).to(dev)
+            self.ckpt = torch.empty(max(int(off[-1]), 1), dtype=_torch_dtype(self.opt), device=dev)
         self.w = w
         self.set_c = gs.c_struct(w)
         size_fn = lib().cfsim_batch_workspace_size if path == "batch" else lib().cfsim_large_workspace_size
@@ -380,6 +394,13 @@ class Batch:
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
 
     def run(self, stream=None):
+        if self.ckpt is not None:
+            _check(lib().cfsim_score_batch_ckpt(
+                self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a), _ptr(self.pair_b), self.n_pairs,
+                ctypes.byref(self.opt), _ptr(self.res), _ptr(self.match), _ptr(self.match_off), _ptr(self.S),
+                _ptr(self.S_off), _ptr(self.ckpt), _ptr(self.ckpt_off), self.checkpoint_every, _ptr(self.ws),
+                self.ws_bytes, _stream(stream)))
+            return
         fn = lib().cfsim_score_batch if self.path == "batch" else lib().cfsim_score_large
         _check(fn(self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a),
                   _ptr(self.pair_b), self.n_pairs, ctypes.byref(self.opt), _ptr(self.res),
@@ -436,7 +457,9 @@ def backward(batch: "Batch", grad_score: torch.Tensor, grad_w: torch.Tensor, che
              stream=None) -> torch.Tensor:
     """Step a10: adds d(sum_p grad_score[p] score_p)/dw to grad_w (FP64, CSR
     order of the set) for the pairs of a batch that has run.  Returns the
-    per-pair status (0, or INVALID_INPUT for skipped pairs)."""
+    per-pair status (0, or INVALID_INPUT for skipped pairs).  A batch built
+    with the same checkpoint_every hands its forward checkpoints over; else
+    the forward is recomputed."""
     if batch.match is None:
         raise ValueError("the backward needs the forward's matchings: build the Batch with want_match=True")
     dev = batch.gs.w.device
@@ -446,10 +469,13 @@ def backward(batch: "Batch", grad_score: torch.Tensor, grad_w: torch.Tensor, che
     ws_bytes = L.cfsim_backward_workspace_size(batch.ctx.handle, ctypes.byref(batch.set_c), batch.n_pairs,
                                                ctypes.byref(batch.opt), int(checkpoint_every))
     ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    use_ck = batch.ckpt is not None and batch.checkpoint_every == int(checkpoint_every)
+    ck, ck_off = (batch.ckpt, batch.ckpt_off) if use_ck else (None, None)
     _check(L.cfsim_score_backward(batch.ctx.handle, ctypes.byref(batch.set_c), _ptr(batch.pair_a),
                                   _ptr(batch.pair_b), batch.n_pairs, ctypes.byref(batch.opt), _ptr(batch.res),
                                   _ptr(batch.match), _ptr(batch.match_off), _ptr(gsc), _ptr(grad_w), _ptr(status),
-                                  int(checkpoint_every), _ptr(ws), ws_bytes, _stream(stream)))
+                                  int(checkpoint_every), _ptr(ck), _ptr(ck_off), _ptr(ws), ws_bytes,
+                                  _stream(stream)))
     return status[: batch.n_pairs]
 
 
@@ -464,7 +490,8 @@ class CfsimScore(torch.autograd.Function):
     @staticmethod
     def forward(ctx_, w, cfctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, checkpoint_every=8):
         w = w.detach().contiguous()
-        b = Batch(cfctx, gs, pair_a, pair_b, dtype=dtype, max_iter=max_iter, tol=tol, want_match=True, w=w)
+        b = Batch(cfctx, gs, pair_a, pair_b, dtype=dtype, max_iter=max_iter, tol=tol, want_match=True, w=w,
+                  checkpoint_every=checkpoint_every)
         b.run()
         ctx_.batch = b
         ctx_.w = w

@@ -73,6 +73,8 @@ struct BwdJob {
     double* grad_w;
     int32_t* pair_status;  // optional: 0 done, CFSIM_INVALID_INPUT skipped
     int ckpt, max_iter;
+    const void* fck;       // forward checkpoints (NULL: the forward is recomputed here)
+    const int64_t* fck_off;
     void* ws;              // gridDim.x slots of slot_bytes
     long long slot_elems, slot_bytes;
     int32_t* queue;
@@ -144,8 +146,10 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
         for (int t = B.rp[r]; t < B.rp[r + 1]; ++t) srcB[t] = r;
     __syncthreads();
 
-    // ---- forward with checkpoints: S_0 = ck[0], S_{c * ckpt} = ck[c]
-    {
+    // ---- forward with checkpoints: S_0 = ck[0], S_{c * ckpt} = ck[c] (only
+    // when the forward call left none: then its checkpoints are read below)
+    const T* fwd_ck = J.fck ? reinterpret_cast<const T*>(J.fck) + J.fck_off[p] : nullptr;
+    if (!fwd_ck) {
         const T* cur = ck;
         for (int k = 0; k < K; ++k) {
             T* dst = slot_buf(seg, J.slot_elems, k & 1);
@@ -184,12 +188,18 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
     __syncthreads();
     for (int s0i = ((K - 1) / J.ckpt) * J.ckpt; s0i >= 0; s0i -= J.ckpt) {
         const int s1 = min(s0i + J.ckpt, K);
-        // recompute S_{s0i+1 .. s1} into seg[1 ..]; seg[0] is the checkpoint
-        const T* Sfirst = slot_buf(ck, J.slot_elems, s0i / J.ckpt);
+        // recompute S_{s0i+1 .. s1} into seg[1 ..] from the segment's first
+        // iterate (S_0, or a checkpoint), with nu_k of every update
+        const T* Sfirst = (s0i == 0 || !fwd_ck) ? slot_buf(ck, J.slot_elems, s0i / J.ckpt)
+                                                : fwd_ck + (long long)(s0i / J.ckpt - 1) * E;
         for (int k = s0i; k < s1; ++k) {
             const T* src = k == s0i ? Sfirst : slot_buf(seg, J.slot_elems, k - s0i);
             T* dst = slot_buf(seg, J.slot_elems, k + 1 - s0i);
-            (void)apply_M(src, dst, T(1.0 / nus[k]), sh, G, red + (k & 1) * NW);
+            const double nu = sqrt(apply_M(src, dst, T(1), sh, G, red + (k & 1) * NW));
+            if (tid == 0) nus[k] = nu;
+            const T inv = T(1.0 / nu);
+            for (long long t = tid; t < E; t += NT) dst[t] *= inv;
+            __syncthreads();
         }
         for (int k = s1 - 1; k >= s0i; --k) {
             const T* Sk = k == s0i ? Sfirst : slot_buf(seg, J.slot_elems, k - s0i);
@@ -198,7 +208,7 @@ __device__ void backward_pair(const BwdJob& J, int p, unsigned char* smem, doubl
             for (long long t = tid; t < E; t += NT) dot += (double)Sk1[t] * (double)Gbar[t];
             dot = block_sum<NW>(dot, red + 2 * NW);
             const T a = T(dot);
-            const T invnu = T(1.0 / nus[k]);
+            const T invnu = T(1.0 / nus[k]);  // written by thread 0 before a barrier of the recompute
             for (long long t = tid; t < E; t += NT) Ybar[t] = (Gbar[t] - a * Sk1[t]) * invnu;
             __syncthreads();
             // edge gradients: every pair of a B edge f = (i -> u) and an A edge
@@ -311,7 +321,8 @@ int backward_grid(int num_cus) { return num_cus * 2; }
 
 int launch_backward(int dtype, const SetRef& set, const int32_t* pair_a, const int32_t* pair_b, int n_pairs,
                     const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
-                    const double* grad_score, double* grad_w, int32_t* pair_status, int ckpt, int max_iter,
+                    const double* grad_score, double* grad_w, int32_t* pair_status, int ckpt,
+                    const void* fck, const int64_t* fck_off, int max_iter,
                     void* ws, long long slot_elems, int grid, hipStream_t stream) {
     BwdJob J;
     J.set = set;
@@ -326,6 +337,8 @@ int launch_backward(int dtype, const SetRef& set, const int32_t* pair_a, const i
     J.pair_status = pair_status;
     J.ckpt = ckpt;
     J.max_iter = max_iter;
+    J.fck = fck;
+    J.fck_off = fck_off;
     const int esize = dtype == CFSIM_F64 ? 8 : 4;
     J.slot_elems = slot_elems;
     J.slot_bytes = backward_slot_bytes(max_iter, ckpt, slot_elems, esize);

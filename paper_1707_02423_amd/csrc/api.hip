@@ -674,10 +674,17 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
 // Plan and bucket kernels of one pass of the batched path on `st`: dtype is
 // the pass's arithmetic type; filter (the FP32 results) restricts the FP64
 // pass of an FP32 call to its near-tie pairs.
+// Forward checkpoints requested by cfsim_score_batch_ckpt (none: ptr NULL).
+struct CkptOut {
+    void* ptr;
+    const int64_t* off;
+    int every;
+};
+
 static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a, const int32_t* pair_b,
                         int64_t n_pairs, const cfsim_options* opt, int dtype, const cfsim_pair_result* filter,
                         cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
-                        const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed) {
+                        const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed, const CkptOut& ck) {
     const int esize = esize_of(dtype);
     cfsim::PlanJob plan{};
     plan.set = ref_of(set);
@@ -708,6 +715,9 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     job.match_off = match_off;
     job.S_out = S_out;
     job.S_off = S_off;
+    job.ckpt = ck.ptr;
+    job.ckpt_off = ck.off;
+    job.ckpt_every = ck.every;
     const int d = dtype_index(dtype);
     // The bucket kernels run one after another on the caller's stream, each
     // with the whole device: a bucket's persistent grid drains its queue
@@ -738,16 +748,16 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
 static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
                          int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
-                         hipStream_t st, bool timed) {
+                         hipStream_t st, bool timed, const CkptOut& ck) {
     const int esize = fp64_final(opt) ? 8 : esize_of(opt->dtype);
     const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
     int e = enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, opt->dtype, nullptr, res, match, match_off, S_out,
-                         S_off, b, st, timed);
+                         S_off, b, st, timed, ck);
     if (e != 0 || !fp64_final(opt)) return e;
     // FP64 pass over the pairs whose FP32 result is a near tie (the schedule
     // arrays are reused: the stream orders the passes)
     return enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, CFSIM_F64, res, res, match, match_off, S_out, S_off, b,
-                        st, false);
+                        st, false, CkptOut{nullptr, nullptr, 0});
 }
 
 static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -778,10 +788,10 @@ static cfsim_status run_large(cfsim_context* ctx, const cfsim_graph_set* set, co
     });
 }
 
-cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
-                               const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
-                               cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
-                               const int64_t* S_off, void* ws, size_t ws_bytes, void* stream) {
+static cfsim_status score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                                cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                                const int64_t* S_off, const CkptOut& ck, void* ws, size_t ws_bytes, void* stream) {
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
@@ -812,16 +822,42 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
     }
     if (ctx->timing || graphs_disabled()) {
         e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st,
-                          ctx->timing != 0);
+                          ctx->timing != 0, ck);
         if (e != 0) return hip_fail(e, "batch launch");
         if (ctx->timing) ctx->timed = 1;
         return ok();
     }
-    const auto key = set_call_key(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    auto key = set_call_key(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+    append_key(key, ck.ptr);
+    append_key(key, ck.off);
+    append_key(key, ck.every);
     return replay_or_capture(ctx, &ctx->graph, &ctx->exec, &ctx->key, key, st, [&](hipStream_t cs) {
         return enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs,
-                             false);
+                             false, ck);
     });
+}
+
+cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                               const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                               cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                               const int64_t* S_off, void* ws, size_t ws_bytes, void* stream) {
+    return score_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
+                       CkptOut{nullptr, nullptr, 0}, ws, ws_bytes, stream);
+}
+
+cfsim_status cfsim_score_batch_ckpt(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                    const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
+                                    cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
+                                    const int64_t* S_off, void* ckpt, const int64_t* ckpt_off,
+                                    int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream) {
+    if (checkpoint_every < 1) return fail(CFSIM_E_INVALID_ARG, "checkpoint_every must be >= 1");
+    if (n_pairs > 0 && (!ckpt || !ckpt_off)) return fail(CFSIM_E_INVALID_ARG, "ckpt or ckpt_off is NULL");
+    if (opt && opt->resize == CFSIM_RESIZE_BILINEAR)
+        return fail(CFSIM_E_UNSUPPORTED, "forward checkpoints on the unscaled operator only");
+    if (opt && fp64_final(opt))
+        return fail(CFSIM_E_UNSUPPORTED, "forward checkpoints with CFSIM_FLAG_FP64_FINAL");
+    return score_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
+                       CkptOut{ckpt, ckpt_off, checkpoint_every}, ws, ws_bytes, stream);
 }
 
 cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -965,7 +1001,8 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
                                   const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
                                   const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
                                   const double* grad_score, double* grad_w, int32_t* pair_status,
-                                  int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream) {
+                                  int32_t checkpoint_every, const void* ckpt, const int64_t* ckpt_off, void* ws,
+                                  size_t ws_bytes, void* stream) {
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
@@ -980,6 +1017,8 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
     if (n_pairs > 0 && (!pair_a || !pair_b || !fwd || !match || !match_off || !grad_score || !grad_w))
         return fail(CFSIM_E_INVALID_ARG, "a pair, forward-result, matching or gradient array is NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
+    if ((ckpt == nullptr) != (ckpt_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "ckpt and ckpt_off must both be given or both be NULL");
     const size_t need = cfsim_backward_workspace_size(ctx, set, n_pairs, opt, checkpoint_every);
     if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
@@ -987,7 +1026,7 @@ cfsim_status cfsim_score_backward(cfsim_context* ctx, const cfsim_graph_set* set
     int e = (int)hipSetDevice(ctx->device);
     if (e != 0) return hip_fail(e, "hipSetDevice");
     e = cfsim::launch_backward(opt->dtype, ref_of(set), pair_a, pair_b, (int)n_pairs, fwd, match, match_off,
-                               grad_score, grad_w, pair_status, checkpoint_every, opt->max_iter, ws,
+                               grad_score, grad_w, pair_status, checkpoint_every, ckpt, ckpt_off, opt->max_iter, ws,
                                global_slot_elems(set->max_nodes), cfsim::backward_grid(ctx->num_cus),
                                static_cast<hipStream_t>(stream));
     if (e != 0) return hip_fail(e, "backward launch");

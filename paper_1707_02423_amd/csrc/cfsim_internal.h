@@ -187,6 +187,12 @@ struct PairJob {
     // elements each); unused by the LDS kernels.
     void* gws;
     long long slot_elems;
+    // Forward checkpoints for the reverse mode (NULL: none): pair p's S_k for
+    // k = c * ckpt_every (c = 1, 2, ...) at ckpt + ckpt_off[p] + (c - 1) n_A n_B,
+    // n_B x n_A row-major, in the arithmetic type
+    void* ckpt;
+    const int64_t* ckpt_off;
+    int ckpt_every;
 };
 
 // Plan: assign every pair a bucket and order each bucket longest first.
@@ -332,7 +338,8 @@ long long backward_slot_bytes(int max_iter, int ckpt, long long slot_elems, int 
 int backward_grid(int num_cus);
 int launch_backward(int dtype, const SetRef& set, const int32_t* pair_a, const int32_t* pair_b, int n_pairs,
                     const cfsim_pair_result* fwd, const int32_t* match, const int64_t* match_off,
-                    const double* grad_score, double* grad_w, int32_t* pair_status, int ckpt, int max_iter,
+                    const double* grad_score, double* grad_w, int32_t* pair_status, int ckpt,
+                    const void* fck, const int64_t* fck_off, int max_iter,
                     void* ws, long long slot_elems, int grid, hipStream_t stream);
 
 // Top-k (topk.hip).

@@ -228,13 +228,37 @@ __device__ __forceinline__ void lds_rows(const unsigned char* Sb, unsigned char*
     }
 }
 
+// Forward checkpoint of update k: S_k = sigma Y_k (Y_k stored in the compute
+// orientation) into dst in the n_B x n_A orientation.  Reads only; the next
+// update reads the same buffer and writes the other.
+template <typename T, int NT>
+__device__ __forceinline__ void write_checkpoint(T* dst, const unsigned char* Yb, T sigma, long long total, int nA,
+                                                 int nC, bool swp) {
+    const T* Y = reinterpret_cast<const T*>(Yb);
+    for (long long o = threadIdx.x; o < total; o += NT) {
+        if (!swp) {
+            dst[o] = Y[o] * sigma;
+        } else {
+            const long long i = o / nA, jj = o - i * nA;
+            dst[o] = Y[jj * nC + i] * sigma;
+        }
+    }
+}
+
+// Checkpoint buffer of pair p (NULL if the call takes none).
+template <typename T>
+__device__ inline T* checkpoint_base(const PairJob& J, int p) {
+    if (!J.ckpt || J.refine) return nullptr;
+    return reinterpret_cast<T*>(J.ckpt) + J.ckpt_off[J.single ? 0 : p];
+}
+
 // Steps a4-a6 with S in LDS (NCH = exact chunk count).  The two buffers hold
 // un-normalised iterates; 1/nu of the stored one (sigma) is folded into the
 // next update and applied in place once, at the end.  Returns the buffer
 // holding the final S.
 template <typename T, int NT, int NCH>
 __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* smem, const PairShape& sh, size_t sbytes,
-                               const Lists<T>& G, bool degenerate, double* red, const int* seg) {
+                               const Lists<T>& G, bool degenerate, double* red, const int* seg, T* ck) {
     constexpr int NW = NT / kWave;
     const int nR = sh.nR, nC = sh.nC;
     const int esz = (int)sizeof(T);
@@ -286,6 +310,9 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
             Nb = const_cast<unsigned char*>(t);
             cur ^= 1;
         }
+        if (ck && k % J.ckpt_every == 0)
+            write_checkpoint<T, NT>(ck + (long long)(k / J.ckpt_every - 1) * nR * nC, Sb, sigma, (long long)nR * nC,
+                                    sh.swap ? nR : nC, nC, sh.swap != 0);
         if (even) {
             out.delta = even_step_delta(es, a_even, inv);
             a_even = inv;
@@ -312,7 +339,7 @@ __device__ __forceinline__ IterOut iterate_lds(const PairJob& J, unsigned char* 
 // folding as the LDS kernel.
 template <typename T, int NT>
 __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairShape& sh, const Lists<T>& G, T* S0, T* S1,
-                                  bool degenerate, double* red) {
+                                  bool degenerate, double* red, T* ck) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
     const int nR = sh.nR, nC = sh.nC, nchunk = sh.nchunk;
@@ -373,6 +400,9 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
             Nb = const_cast<unsigned char*>(t);
             cur ^= 1;
         }
+        if (ck && k % J.ckpt_every == 0)
+            write_checkpoint<T, NT>(ck + (long long)(k / J.ckpt_every - 1) * nR * nC, Sb, sigma, (long long)nR * nC,
+                                    sh.swap ? nR : nC, nC, sh.swap != 0);
         if (even) {
             out.delta = even_step_delta(es, a_even, inv);
             a_even = inv;
@@ -869,11 +899,12 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
         const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
         if constexpr (NT == kWave) order_rows<T, NT>(G, nR, G.rstate, s_seg);  // one wave: no barrier needed
         if (NCHMAX == 1 || sh.nchunk == 1)
-            it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
+            it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red, s_seg, checkpoint_base<T>(J, p));
         else if (NCHMAX == 2 || sh.nchunk == 2)
-            it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
+            it = iterate_lds<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, sh, sbytes, G, degenerate, red, s_seg,
+                                                           checkpoint_base<T>(J, p));
         else
-            it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red, s_seg);
+            it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red, s_seg, checkpoint_base<T>(J, p));
     }
     // The pair's graphs, shape and lists again, from fresh reads of the
     // arguments (the same values: the iteration does not change them).
@@ -912,7 +943,7 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
     T* S1 = slot + J.slot_elems;
     const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
     const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, S0, s0);
-    const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, degenerate, red);
+    const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, degenerate, red, checkpoint_base<T>(J, p));
     match_and_write<T, NT>(J, p, A, B, sh, it.final_buf ? S1 : S0, it.final_buf ? S0 : S1, G, it, res, red, s_count);
 }
 

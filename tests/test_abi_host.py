@@ -249,7 +249,7 @@ def test_resize_limits_and_unsupported_calls():
     s = _set()
     assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None) == -6
     assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
-                                  0x1000, 0x1000, 0x1000, None, 8, 0x1000, 1 << 40, None) == -6
+                                  0x1000, 0x1000, 0x1000, None, 8, None, None, 0x1000, 1 << 40, None) == -6
     opt_long = cf.options("f32", max_iter=5000, resize="bilinear")
     A, B = _graph(), _graph(4, 3)
     assert _call_score(A, B, opt_long) == -6
@@ -283,7 +283,7 @@ def test_fp64_final_refused_where_it_does_not_apply():
     assert L.cfsim_score_large(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None, None,
                                None, None, 0x1000, 1 << 40, None) == -6
     assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
-                                  0x1000, 0x1000, 0x1000, None, 8, 0x1000, 1 << 40, None) == -6
+                                  0x1000, 0x1000, 0x1000, None, 8, None, None, 0x1000, 1 << 40, None) == -6
     # the FP64 pass needs FP64-sized global-kernel slots
     plain = cf.options("f32")
     a = L.cfsim_batch_workspace_size(None, ctypes.byref(s), 10, ctypes.byref(plain))
@@ -367,3 +367,21 @@ def test_tune_class_and_table_validation():
     assert L.cfsim_context_set_tune(None, cf.F32, arr, cf.TUNE_CLASSES) == -1
     assert "context" in L.cfsim_last_error().decode()
     assert L.cfsim_context_get_tune(None, cf.F32, arr, cf.TUNE_CLASSES) == -1
+
+
+def test_forward_checkpoint_arguments_checked_on_the_host():
+    L = cf.lib()
+    s = _set()
+    opt = cf.options("f32")
+    call = lambda ck, off, every, o=opt: L.cfsim_score_batch_ckpt(
+        None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(o), 0x1000, None, None, None, None, ck, off, every,
+        0x1000, 1 << 40, None)
+    assert call(0x1000, 0x1000, 0) == -1 and "checkpoint_every" in L.cfsim_last_error().decode()
+    assert call(None, 0x1000, 8) == -1 and "ckpt" in L.cfsim_last_error().decode()
+    assert call(0x1000, 0x1000, 8, cf.options("f32", resize="bilinear")) == -6
+    assert call(0x1000, 0x1000, 8, cf.options("f32", fp64_final=True)) == -6
+    assert call(0x1000, 0x1000, 8) == -1 and "context" in L.cfsim_last_error().decode()
+    # the backward takes both checkpoint arrays or neither
+    assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
+                                  0x1000, 0x1000, 0x1000, None, 8, 0x1000, None, 0x1000, 1 << 40, None) == -1
+    assert "ckpt" in L.cfsim_last_error().decode()

@@ -129,3 +129,41 @@ def test_autograd_function_matches_finite_differences(cf, ctx):
                 off = edge_off[pa[p] if which == "A" else pb[p]]
                 worst = max(worst, abs(g[off + e] - fd) / max(1.0, abs(fd)))
     assert worst < 5e-4, worst
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_backward_from_forward_checkpoints_matches_recompute(cf, ctx, dtype, tol):
+    """A forward that leaves checkpoints (cfsim_score_batch_ckpt) gives the
+    same forward results as the plain batch, and the reverse started from
+    them agrees with the reverse that recomputes the forward (the two differ
+    only in the rounding of the recomputed iterates)."""
+    w = config_graphs(3, scale=24 / 1024)
+    gs = cf.pack(ctx, w["graphs"])
+    pa, pb = w["pair_a"], w["pair_b"]
+    plain = cf.Batch(ctx, gs, pa, pb, dtype=dtype, want_match=True)
+    ck = cf.Batch(ctx, gs, pa, pb, dtype=dtype, want_match=True, checkpoint_every=8)
+    plain.run()
+    ck.run()
+    torch.cuda.synchronize()
+    assert plain.results().tobytes() == ck.results().tobytes()
+    gsc = torch.linspace(0.5, 1.5, len(pa), dtype=torch.float64)
+    g_re = torch.zeros(gs.total_edges, dtype=torch.float64, device="cuda")
+    g_ck = torch.zeros_like(g_re)
+    s1 = cf.backward(plain, gsc, g_re, checkpoint_every=8)
+    s2 = cf.backward(ck, gsc, g_ck, checkpoint_every=8)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(s1)) == 0 and int(torch.count_nonzero(s2)) == 0
+    a, b = g_re.cpu().numpy(), g_ck.cpu().numpy()
+    assert np.abs(a - b).max() <= tol * np.abs(a).max(), np.abs(a - b).max() / np.abs(a).max()
+    # the checkpoints are the forward's iterates S_8, S_16, ... of every pair
+    p = int(np.argmax([w["graphs"][x].n * w["graphs"][y].n for x, y in zip(pa, pb)]))
+    ga, gb = w["graphs"][pa[p]], w["graphs"][pb[p]]
+    A = oracle.transition_matrix(ga.n, ga.src, ga.dst, ga.count)
+    B = oracle.transition_matrix(gb.n, gb.src, gb.dst, gb.count)
+    its = oracle.coupled_iteration(A, B, 200, 0.0, keep_iterates=True)[5]
+    o = int(ck.ckpt_off[p])
+    E = ga.n * gb.n
+    for c in (1, 5, 20):
+        got = ck.ckpt[o + (c - 1) * E:o + c * E].double().cpu().numpy().reshape(gb.n, ga.n)
+        ref = its[8 * c]
+        assert np.max(np.abs(got - ref)) <= (1e-10 if dtype == "f64" else 1e-5) * np.max(ref)
