@@ -4,8 +4,9 @@ Only `tests/`, `__graft_entry__.smoke()` and the `cpu_baseline` leg of
 `bench.py` may import or call anything in this package.  The product path
 (the HIP library and its Python binding) never touches it, and this package
 imports nothing from the product.  See `oracle/cfsim_ref.py` for the
-readings of the paper it implements, and `oracle/bf16_model.py` for the
-model of the BF16 matrix-core variant.
+readings of the paper it implements, `oracle/bf16_model.py` for the
+model of the BF16 matrix-core variant and `oracle/distances.py` for the
+elementwise distances of Table 1.
 """
 from .cfsim_ref import (  # noqa: F401
     CONVERGED, HIT_MAX_ITER, DEGENERATE, INVALID_INPUT,
@@ -14,3 +15,4 @@ from .cfsim_ref import (  # noqa: F401
     backward, edge_gradients, topk, PairResult,
 )
 from .bf16_model import round_bf16, coupled_iteration_bf16  # noqa: F401
+from .distances import NAMES as DISTANCE_NAMES, scaled_pair, elementwise_distances, pair_distances  # noqa: F401

@@ -174,3 +174,68 @@ def test_pathfinder_fixture_invariants_both_modes():
             assert r.S.shape == (6, 6)
         else:
             assert r.S.shape == (6, 4)
+
+
+# ---------------------------------------------------------------- distances
+def _distance_pins_hold(fn) -> bool:
+    """The scipy, set-Jaccard and scaled-pair pins of tests/test_distance_pins.py
+    applied to `fn` in place of the oracle's elementwise_distances."""
+    from tests.test_distance_pins import _corner_aligned_sample, _tm, _vectors, scipy_measures
+    ok = True
+    for seed in range(3):
+        x, y = _vectors(seed)
+        ok &= np.allclose(fn(x, y, 3.0), scipy_measures(x, y, 3.0), rtol=1e-12, atol=0)
+    rng = np.random.default_rng(1)
+    xb, yb = rng.random(64) < 0.3, rng.random(64) < 0.5
+    X, Y = set(np.flatnonzero(xb)), set(np.flatnonzero(yb))
+    ok &= np.isclose(fn(xb.astype(float), yb.astype(float), 3.0)[3], len(X ^ Y) / len(X | Y), rtol=1e-15)
+    A, B = _tm(5, 15), _tm(9, 45)
+    As = _corner_aligned_sample(A, 9)
+    ok &= np.allclose(fn(*oracle.scaled_pair(A, B), 3.0), scipy_measures(As.ravel(), B.ravel(), 3.0),
+                      rtol=1e-12, atol=1e-15)
+    return bool(ok)
+
+
+def _with_sums(transform):
+    def fn(x, y, p=3.0):
+        x = np.asarray(x, float).ravel()
+        y = np.asarray(y, float).ravel()
+        return transform(x, y, p)
+    return fn
+
+
+MUTANT_DISTANCES = {
+    "euclidean without the root": _with_sums(
+        lambda x, y, p: np.r_[np.sum((x - y) ** 2), oracle.elementwise_distances(x, y, p)[1:]]),
+    "manhattan of squares": _with_sums(
+        lambda x, y, p: np.r_[oracle.elementwise_distances(x, y, p)[:1], np.sum((x - y) ** 2),
+                              oracle.elementwise_distances(x, y, p)[2:]]),
+    "minkowski without the root": _with_sums(
+        lambda x, y, p: np.r_[oracle.elementwise_distances(x, y, p)[:2], np.sum(np.abs(x - y) ** p),
+                              oracle.elementwise_distances(x, y, p)[3:]]),
+    "jaccard denominator adds the cross term": _with_sums(
+        lambda x, y, p: np.r_[oracle.elementwise_distances(x, y, p)[:3],
+                              np.sum((x - y) ** 2) / (x @ x + y @ y + x @ y),
+                              oracle.elementwise_distances(x, y, p)[4:]]),
+    "cosine without the square roots": _with_sums(
+        lambda x, y, p: np.r_[oracle.elementwise_distances(x, y, p)[:4], 1 - (x @ y) / ((x @ x) * (y @ y))]),
+}
+
+
+def test_unmutated_distances_pass():
+    assert _distance_pins_hold(oracle.elementwise_distances)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANT_DISTANCES))
+def test_distance_mutants_fail_the_pins(name):
+    assert not _distance_pins_hold(MUTANT_DISTANCES[name])
+
+
+def test_unscaled_pair_fails_the_scaled_pin():
+    from tests.test_distance_pins import _corner_aligned_sample, _tm, scipy_measures
+    A, B = _tm(5, 15), _tm(9, 45)
+    # A mutant that scales by nearest-node repetition instead of the order-1 spline.
+    idx = np.rint(np.arange(9) * 4 / 8).astype(int)
+    x = A[np.ix_(idx, idx)].ravel()
+    want = scipy_measures(_corner_aligned_sample(A, 9).ravel(), B.ravel(), 3.0)
+    assert not np.allclose(oracle.elementwise_distances(x, B.ravel(), 3.0), want, rtol=1e-12)
