@@ -272,8 +272,8 @@ def plain_pair_leg(ctx, stream, reps=200):
 def workload_legs(ctx, stream, reps=3):
     """The other hot-path rows, each on its own synthetic workload: the plain
     12 x 16 pair, large pairs (tiled path), query-vs-database with top-16,
-    the reverse mode, and the scale-to-common-size mode of the all-pairs
-    batch.  Inputs resident in HBM; every time is the average of `reps` timed
+    the reverse mode, the scale-to-common-size mode of the all-pairs batch,
+    and the elementwise distances of Table 1.  Inputs resident in HBM; every time is the average of `reps` timed
     calls after one warm-up; every leg states its error against the FP64 GPU
     path (itself parity-tested against the CPU oracle)."""
     import torch
@@ -418,6 +418,34 @@ def workload_legs(ctx, stream, reps=3):
                                                            zip(b.matches(), b64.matches()))),
                          **errs)
     del b, b64, gs
+
+    # f1: Table 1's five elementwise distances (Minkowski p = 3) of every pair
+    # of the 256-CFG batch and of the 64 large pairs, FP64.  Work per entry of
+    # the M x M common-size matrices: the interpolated entry (9 flops) and
+    # the six sums (13 flops).
+    dist = {}
+    for key, idx, label in (("all_pairs", 1, "all 32,640 pairs of the 256-CFG batch, n ~ U[8,128]"),
+                            ("large_pairs", 2, "64 pairs of synthetic CFGs, n ~ U[512,2048]")):
+        w = config_graphs(idx)
+        gs = cf.pack(ctx, w["graphs"])
+        dev = gs.w.device
+        pa = torch.as_tensor(w["pair_a"], device=dev)
+        pb = torch.as_tensor(w["pair_b"], device=dev)
+        d = cf.distances(ctx, gs, pa, pb, stream=stream)
+        torch.cuda.synchronize()
+        ms = _time_ms(lambda: cf.distances(ctx, gs, pa, pb, stream=stream), reps, stream)
+        sizes = np.diff(gs.node_off).astype(np.float64)
+        M = np.maximum(sizes[w["pair_a"]], sizes[w["pair_b"]])
+        entries = float(np.sum(M * M))
+        tflops = 22.0 * entries / (ms * 1e-3) / 1e12
+        dist[key] = dict(workload=label + ", five distances on the common-size matrices, FP64",
+                         ms_per_call=ms, pairs_per_s=len(w["pair_a"]) / (ms * 1e-3),
+                         entries_per_s=entries / (ms * 1e-3),
+                         alu_roofline=dict(bound="alu", achieved=tflops, peak=78.6, unit="TFLOP/s",
+                                           frac=tflops / 78.6),
+                         all_finite=bool(torch.isfinite(d).all()))
+        del gs, d
+    out["distances"] = dist
     return out
 
 
@@ -426,8 +454,10 @@ def profile_only(spec: str):
       pair:NA:NB:DTYPE:MAX_ITER:REPS  the plain path on one seeded pair
                                       (tol 0: every launch runs MAX_ITER updates)
       workload:NAME:REPS              NAME = batch, large, largemfma, resize,
-                                      query, backward or fp64final; FP32, REPS
-                                      calls after one warm-up"""
+                                      query, backward or fp64final (FP32), or
+                                      distances / distlarge (the elementwise
+                                      distances of the batch / the large pairs,
+                                      FP64); REPS calls after one warm-up"""
     import torch
     from paper_1707_02423_amd import cfsim as cfm
     from cfgsynth import Grammar, config_graphs, make_cfg
@@ -443,9 +473,19 @@ def profile_only(spec: str):
     elif f[0] == "workload" and len(f) == 3:
         name, reps = f[1], int(f[2])
         idx = {"batch": 1, "resize": 1, "fp64final": 1, "large": 2, "largemfma": 2, "backward": 3,
-               "query": 4}.get(name)
+               "query": 4, "distances": 1, "distlarge": 2}.get(name)
         if idx is None:
             raise SystemExit(f"unknown workload {name!r}")
+        if name in ("distances", "distlarge"):
+            w = config_graphs(idx)
+            gs = cfm.pack(ctx, w["graphs"])
+            pa = torch.as_tensor(w["pair_a"], device=gs.w.device)
+            pb = torch.as_tensor(w["pair_b"], device=gs.w.device)
+            for _ in range(reps + 1):
+                cfm.distances(ctx, gs, pa, pb)
+            torch.cuda.synchronize()
+            print("done", spec, flush=True)
+            return
         w = config_graphs(idx)
         kw = dict(path="large") if name in ("large", "largemfma") else {}
         kw.update(dict(mfma=True) if name == "largemfma" else {})

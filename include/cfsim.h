@@ -398,6 +398,44 @@ size_t cfsim_topk_workspace_size(int64_t n, int32_t k);
 cfsim_status cfsim_topk(cfsim_context* ctx, const double* scores, int64_t n, int64_t stride, int32_t k,
                         int32_t* idx_out, double* score_out, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Table 1's elementwise distances of many pairs (Section 4.2, Pairwise
+ * Comparison), computed on the pair's two transition matrices once both are
+ * at the common size M = max(n_A, n_B) (Section 4 and Section 4.1: the
+ * smaller matrix X becomes R X R^T with the order-1 interpolation R of the
+ * resize option above; the larger one is kept; equal sizes are compared as
+ * they are).  With x and y the two M x M matrices read as vectors, d = x - y:
+ *   out[5 q + CFSIM_DIST_EUCLIDEAN] = sqrt(sum d^2)
+ *   out[5 q + CFSIM_DIST_MANHATTAN] = sum |d|
+ *   out[5 q + CFSIM_DIST_MINKOWSKI] = (sum |d|^p)^(1/p)
+ *   out[5 q + CFSIM_DIST_JACCARD]   = sum d^2 / (sum x^2 + sum y^2 - sum x y)
+ *                                     (0 when x = y = 0)
+ *   out[5 q + CFSIM_DIST_COSINE]    = 1 - sum x y / (||x|| ||y||)
+ *                                     (NaN when x or y is 0)
+ * All five are symmetric, so which graph of the pair is A does not matter.
+ * Pair q compares graphs pair_a[q] and pair_b[q] of `set`; a pair with an
+ * index outside [0, n_graphs), or a graph above set->max_nodes, gets five
+ * NaN.  Device buffers: pair_a and
+ * pair_b [n_pairs], out [5 n_pairs] (FP64), ws of
+ * cfsim_distances_workspace_size() bytes.  p is the Minkowski order (the
+ * paper gives none; 3 is the usual choice): finite and >= 1, else
+ * CFSIM_E_INVALID_ARG.  Sums are FP64; the scaled matrices are never stored
+ * (each entry is evaluated from the CSR rows), so set->max_nodes may be up
+ * to 32,768.  Results do not depend on the launch shape.
+ */
+#define CFSIM_NUM_DISTANCES 5
+enum {
+    CFSIM_DIST_EUCLIDEAN = 0,
+    CFSIM_DIST_MANHATTAN = 1,
+    CFSIM_DIST_MINKOWSKI = 2,
+    CFSIM_DIST_JACCARD = 3,
+    CFSIM_DIST_COSINE = 4
+};
+size_t cfsim_distances_workspace_size(const cfsim_graph_set* set, int64_t n_pairs);
+cfsim_status cfsim_distances(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                             const int32_t* pair_b, int64_t n_pairs, double p, double* out, void* ws,
+                             size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -103,6 +103,9 @@ SIGNATURES = {
     "cfsim_context_get_tune": (ctypes.c_int, [_P, _I32, _P, _I32]),
     "cfsim_topk_workspace_size": (_SZ, [_I64, _I32]),
     "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "cfsim_distances_workspace_size": (_SZ, [ctypes.POINTER(GraphSetC), _I64]),
+    "cfsim_distances": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.c_double, _P, _P, _SZ,
+                                       _P]),
 }
 
 
@@ -451,6 +454,33 @@ def topk(ctx: Context, scores: torch.Tensor, k: int, stride: int = 1, n: int | N
     _check(lib().cfsim_topk(ctx.handle, _ptr(scores), n, stride, k, _ptr(idx), _ptr(val), _ptr(ws), ws_bytes,
                             _stream(stream)))
     return idx, val
+
+
+NUM_DISTANCES = 5
+DISTANCE_NAMES = ("euclidean", "manhattan", "minkowski", "jaccard", "cosine")
+
+
+def distances(ctx: Context, gs: GraphSet, pair_a, pair_b, p: float = 3.0, stream=None) -> torch.Tensor:
+    """Table 1's five elementwise distances of every pair (cfsim_distances):
+    a float64 device tensor [n_pairs, 5] in the order of DISTANCE_NAMES,
+    computed on the two transition matrices at their common size.  The pair
+    indices may be host arrays or int32 device tensors (used in place)."""
+    dev = gs.row_ptr.device
+
+    def on_device(x):
+        if isinstance(x, torch.Tensor):
+            return x.to(device=dev, dtype=torch.int32).contiguous()
+        return torch.as_tensor(np.asarray(x, np.int32), device=dev)
+    pa, pb = on_device(pair_a), on_device(pair_b)
+    n = int(pa.numel())
+    out = torch.empty((n, NUM_DISTANCES), dtype=torch.float64, device=dev)
+    set_c = gs.c_struct()
+    L = lib()
+    ws_bytes = L.cfsim_distances_workspace_size(ctypes.byref(set_c), n)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(L.cfsim_distances(ctx.handle, ctypes.byref(set_c), _ptr(pa), _ptr(pb), n, float(p), _ptr(out), _ptr(ws),
+                             ws_bytes, _stream(stream)))
+    return out
 
 
 def backward(batch: "Batch", grad_score: torch.Tensor, grad_w: torch.Tensor, checkpoint_every: int = 8,

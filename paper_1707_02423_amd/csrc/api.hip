@@ -1058,4 +1058,36 @@ cfsim_status cfsim_topk(cfsim_context* ctx, const double* scores, int64_t n, int
     return ok();
 }
 
+// ------------------------------------------------------------------ elementwise distances (Table 1)
+size_t cfsim_distances_workspace_size(const cfsim_graph_set* set, int64_t n_pairs) {
+    if (!set || set->max_nodes < 1 || set->max_nodes > 32768 || n_pairs < 1) return 0;
+    return align256((size_t)(n_pairs + 1) * 8) +
+           align256((size_t)n_pairs * (size_t)cfsim::dist_tasks_bound(set->max_nodes) * cfsim::kDistSums * 8);
+}
+
+cfsim_status cfsim_distances(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                             const int32_t* pair_b, int64_t n_pairs, double p, double* out, void* ws,
+                             size_t ws_bytes, void* stream) {
+    cfsim_status s;
+    if ((s = check_set(set)) != CFSIM_OK) return s;
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > INT32_MAX - 1) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-2 pairs in one call");
+    if (!(p >= 1.0) || !std::isfinite(p)) return fail(CFSIM_E_INVALID_ARG, "the Minkowski order must be finite and >= 1");
+    if (set->max_nodes > 32768) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 32768");
+    if (n_pairs > 0 && (!pair_a || !pair_b || !out)) return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or out is NULL");
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_pairs == 0) return ok();
+    const size_t need = cfsim_distances_workspace_size(set, n_pairs);
+    if (ws_bytes < need || !ws) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    unsigned char* base = static_cast<unsigned char*>(ws);
+    int64_t* task_off = reinterpret_cast<int64_t*>(base);
+    double* part = reinterpret_cast<double*>(base + align256((size_t)(n_pairs + 1) * 8));
+    e = cfsim::launch_distances(ref_of(set), set->max_nodes, pair_a, pair_b, (int)n_pairs, p, out, task_off, part,
+                                cfsim::dist_grid(num_cus_of(ctx)), static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "distance launch");
+    return ok();
+}
+
 }  // extern "C"

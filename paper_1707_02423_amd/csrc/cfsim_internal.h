@@ -349,4 +349,26 @@ size_t topk_stage2_lds(long long n, int k);
 int launch_topk(const double* scores, long long n, long long stride, int k, int32_t* idx_out, double* score_out,
                 void* ws, hipStream_t stream);
 
+// Elementwise distances (distances.hip).  A pair of common size M is cut into
+// row chunks of dist_rows(M) rows: about kDistEntries entries per chunk, at
+// most kDistMaxTasks chunks per pair.
+constexpr int kDistEntries = 2048;
+constexpr int kDistMaxTasks = 64;
+constexpr int kDistSums = 6;
+__host__ __device__ inline int dist_rows(int M) {
+    int r = (M + kDistMaxTasks - 1) / kDistMaxTasks;
+    const int by_entries = kDistEntries / M;
+    if (by_entries > r) r = by_entries;
+    if (r < 1) r = 1;
+    return r < M ? r : M;
+}
+__host__ __device__ inline int dist_tasks(int M) {
+    const int r = dist_rows(M);
+    return (M + r - 1) / r;
+}
+long long dist_tasks_bound(int max_nodes);
+int dist_grid(int num_cus);
+int launch_distances(const SetRef& set, int max_nodes, const int32_t* pa, const int32_t* pb, int n_pairs, double p,
+                     double* out, int64_t* task_off, double* part, int grid, hipStream_t stream);
+
 }  // namespace cfsim

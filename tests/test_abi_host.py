@@ -385,3 +385,42 @@ def test_forward_checkpoint_arguments_checked_on_the_host():
     assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
                                   0x1000, 0x1000, 0x1000, None, 8, 0x1000, None, 0x1000, 1 << 40, None) == -1
     assert "ckpt" in L.cfsim_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,n_pairs,p,ws,code,text", [
+    (dict(n_graphs=0), 5, 3.0, 1 << 20, -2, "n_graphs"),
+    ({}, -1, 3.0, 1 << 20, -1, "n_pairs"),
+    ({}, 5, 0.5, 1 << 20, -1, "Minkowski"),
+    ({}, 5, float("inf"), 1 << 20, -1, "Minkowski"),
+    ({}, 5, float("nan"), 1 << 20, -1, "Minkowski"),
+    (dict(max_nodes=40000), 5, 3.0, 1 << 20, -6, "max_nodes"),
+    ({}, 5, 3.0, 1 << 20, -1, "context"),
+])
+def test_distances_validation(kw, n_pairs, p, ws, code, text):
+    L = cf.lib()
+    s = _set(**kw)
+    assert L.cfsim_distances(None, ctypes.byref(s), 0x1000, 0x1000, n_pairs, p, 0x1000, 0x1000, ws, None) == code
+    assert text in L.cfsim_last_error().decode()
+
+
+def test_distances_null_buffers_and_workspace():
+    L = cf.lib()
+    s = _set()
+    P = 0x1000
+    assert L.cfsim_distances(P, ctypes.byref(s), None, P, 5, 3.0, P, P, 1 << 20, None) == -1
+    assert L.cfsim_distances(P, ctypes.byref(s), P, P, 5, 3.0, None, P, 1 << 20, None) == -1
+    need = L.cfsim_distances_workspace_size(ctypes.byref(s), 5)
+    assert need > 0
+    assert L.cfsim_distances(P, ctypes.byref(s), P, P, 5, 3.0, P, P, need - 1, None) == -5
+    assert "workspace" in L.cfsim_last_error().decode()
+    # No pair: nothing to do, no workspace needed and no HIP call.
+    assert L.cfsim_distances(P, ctypes.byref(s), None, None, 0, 3.0, None, None, 0, None) == 0
+
+
+def test_distances_workspace_bound_covers_every_size():
+    L = cf.lib()
+    # Chunk partials: at most 64 chunks of six doubles per pair.
+    small = L.cfsim_distances_workspace_size(ctypes.byref(_set(max_nodes=8)), 1000)
+    large = L.cfsim_distances_workspace_size(ctypes.byref(_set(max_nodes=2048)), 1000)
+    assert small >= 1001 * 8 + 1000 * 48 and large >= 1001 * 8 + 1000 * 64 * 48
+    assert L.cfsim_distances_workspace_size(ctypes.byref(_set(max_nodes=40000)), 10) == 0
