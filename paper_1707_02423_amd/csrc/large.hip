@@ -39,12 +39,10 @@ namespace {
 using namespace tiled;
 using dev::better;
 using dev::uni;
-using dev::wave_argmax;
 using dev::wave_sum;
 
 constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
 constexpr int kFinishThreads = 1024;
-constexpr int kCache = 8;  // cached partners per line in the matching
 constexpr int kLS = 2;                          // successors per lane column in registers
 constexpr int kLP = 3;                          // predecessors per lane column in registers
 constexpr int kSlotU = 0;                       // resize: U_k in slot k % 4
@@ -662,9 +660,266 @@ __global__ __launch_bounds__(kStepThreads) void large_gram(LargeJob J, int k) {
 }
 
 // ---------------------------------------------------------------- finish
-// One workgroup per pair: form the final S (Y_f / nu_f; for a resized pair
-// the expansion U_f R^T / nu_f to M x M; S_0 for a degenerate pair), greedy
-// matching, outputs.
+// Three kernels after the last update.  large_final forms the final S (Y_f /
+// nu_f; for a resized pair the expansion U_f R^T / nu_f to M x M; S_0 for a
+// degenerate pair) and S^T in 32 x 32 tiles through LDS, many workgroups per
+// pair.  large_sort_lines sorts every line (each row of S and each row of
+// S^T) in the greedy order, many workgroups per pair.  large_finish runs the
+// matching rounds on the sorted lines and writes the outputs, one workgroup
+// per pair.
+
+// Pair p's final S and S^T, and the slot that receives the sorted lines.
+template <typename T>
+struct FinalBufs {
+    T* S;
+    T* St;
+    uint16_t* lists;  // row lines [nR][nC], then column lines [nC][nR]
+    int nR, nC;
+};
+
+template <typename T>
+__device__ inline FinalBufs<T> final_bufs(const LargeJob& J, int p, const LargeState* s) {
+    FinalBufs<T> b;
+    const int f = s->final_step;
+    const bool rz = s->rz != 0;
+    b.nR = rz ? s->M : s->nB;   // rows of S (B side)
+    b.nC = rz ? s->M : s->nA;   // columns of S (A side)
+    b.S = rz ? buf_of<T>(J, p, kSlotS) : buf_of<T>(J, p, f & 3);
+    b.St = rz ? buf_of<T>(J, p, kSlotU + ((f + 1) & 3)) : buf_of<T>(J, p, (f + 1) & 3);
+    b.lists = reinterpret_cast<uint16_t*>(rz ? buf_of<T>(J, p, kSlotU + ((f + 2) & 3)) : buf_of<T>(J, p, (f + 2) & 3));
+    return b;
+}
+
+constexpr int kFinalThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kFinalThreads) void large_final(LargeJob J) {
+    __shared__ T tile[32][33];
+    const int p = blockIdx.y;
+    const LargeState* s = J.st + p;
+    if (s->status & CFSIM_INVALID_INPUT) return;
+    const FinalBufs<T> fb = final_bufs<T>(J, p, s);
+    const int nR = fb.nR, nC = fb.nC, f = s->final_step;
+    const bool rz = s->rz != 0;
+    const T c0v = T(1.0 / sqrt((double)nR * (double)nC));
+    const double sig = f > 0 ? 1.0 / s->nu_k[f & 3] : 1.0;
+    const T sigT = T(sig);
+    const T* U = rz ? buf_of<T>(J, p, kSlotU + (f & 3)) : nullptr;
+    const int m = s->nC, M = s->M;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int ntc = (nC + 31) / 32, ntiles = ((nR + 31) / 32) * ntc;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int i0 = (t / ntc) * 32, j0 = (t % ntc) * 32;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + ty + 8 * k, j = j0 + tx;
+            if (i < nR && j < nC) {
+                T v;
+                if (f == 0) {
+                    v = c0v;
+                } else if (!rz) {
+                    v = fb.S[(long long)i * nC + j] * sigT;
+                } else {
+                    // state row r (node of the larger graph), expanded column qq;
+                    // the state holds S (swap = 0) or S^T (swap = 1)
+                    const int r = s->swap ? j : i, qq = s->swap ? i : j;
+                    const Interp ip = interp_at(qq, m, M);
+                    const T* urow = U + (long long)r * m;
+                    double y;
+                    if (ip.r1 == ip.r0)
+                        y = (double)urow[ip.r0] * sig;
+                    else
+                        y = (1.0 - ip.f) * ((double)urow[ip.r0] * sig) + ip.f * ((double)urow[ip.r1] * sig);
+                    v = T(y);
+                }
+                fb.S[(long long)i * nC + j] = v;
+                tile[ty + 8 * k][tx] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = j0 + ty + 8 * k, r = i0 + tx;
+            if (c < nC && r < nR) fb.St[(long long)c * nR + r] = tile[tx][ty + 8 * k];
+        }
+        __syncthreads();
+    }
+}
+
+// Sort keys of the greedy order along a line: value descending (NaN after
+// every number), then partner index ascending (FP32: one 64-bit word).
+__device__ inline uint64_t line_key(float v, int y) { return ((uint64_t)dev::desc_bits(v) << 32) | (uint32_t)y; }
+__device__ inline uint64_t line_key(double v, int) { return dev::desc_bits(v); }
+
+constexpr int kSortThreads = 256;
+constexpr int kSortElems = 2048;  // elements per workgroup pass when lines are short
+
+__host__ __device__ inline int pow2_at_least(int n) {
+    int q = 1;
+    while (q < n) q <<= 1;
+    return q;
+}
+
+// Every line of pair blockIdx.y in the greedy order: its partner indices in
+// that order, as 16-bit words (nodes < 8192).  Lines take P slots, P the
+// next power of two >= max(nR, nC), and are sorted G at a time by one
+// bitonic network on G * P elements (P < kSortElems: G = kSortElems / P).
+// Merge levels with a partner distance of 8 or more exchange through LDS;
+// the three innermost levels run in registers on aligned groups of 8.  FP32
+// keys hold the partner index in their low word; FP64 keys keep it apart.
+__device__ inline bool key_gt(uint64_t ka, int ia, uint64_t kb, int ib) { return ka > kb || (ka == kb && ia > ib); }
+
+template <typename T>
+struct SortBuf {
+    uint64_t* k;
+    int* i;  // FP64 only
+    __device__ void get(int e, uint64_t& kk, int& ii) const {
+        kk = k[e];
+        ii = sizeof(T) == 8 ? i[e] : 0;
+    }
+    __device__ void put(int e, uint64_t kk, int ii) const {
+        k[e] = kk;
+        if constexpr (sizeof(T) == 8) i[e] = ii;
+    }
+    __device__ int index_of(uint64_t kk, int ii) const { return sizeof(T) == 8 ? ii : (int)(uint32_t)kk; }
+};
+
+// Compare-exchange levels j = J0, J0 / 2, ..., 1 of merge size k on the 8
+// elements at e0 (aligned to 8; J0 <= 4).
+template <typename T>
+__device__ inline void sort8(const SortBuf<T>& B, int e0, int k, int J0, int P) {
+    uint64_t kk[8];
+    int ii[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a) B.get(e0 + a, kk[a], ii[a]);
+    for (int j = J0; j > 0; j >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+            if (a & j) continue;
+            const int i = e0 + a;
+            const bool up = k == P || (i & k) == 0;
+            if (a + j < 8 && key_gt(kk[a], ii[a], kk[a + j], ii[a + j]) == up) {
+                const uint64_t tk = kk[a];
+                kk[a] = kk[a + j];
+                kk[a + j] = tk;
+                const int ti = ii[a];
+                ii[a] = ii[a + j];
+                ii[a + j] = ti;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) B.put(e0 + a, kk[a], ii[a]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void large_sort_lines(LargeJob J) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int p = blockIdx.y;
+    const LargeState* s = J.st + p;
+    if (s->status & CFSIM_INVALID_INPUT) return;
+    const FinalBufs<T> fb = final_bufs<T>(J, p, s);
+    const int nR = fb.nR, nC = fb.nC;
+    const int P = pow2_at_least(nR > nC ? nR : nC);
+    const int G = P >= kSortElems ? 1 : kSortElems / P;
+    const int E = G * P, lgP = __builtin_ctz((unsigned)P);
+    SortBuf<T> B;
+    B.k = reinterpret_cast<uint64_t*>(smem);
+    B.i = reinterpret_cast<int*>(smem + (size_t)E * 8);
+    const int lines = nR + nC;
+    for (int g = blockIdx.x; g * G < lines; g += gridDim.x) {
+        for (int e = threadIdx.x; e < E; e += kSortThreads) {
+            const int x = g * G + (e >> lgP), y = e & (P - 1);
+            uint64_t k = ~0ull;
+            int id = INT_MAX;
+            if (x < lines) {
+                const bool row = x < nR;
+                if (y < (row ? nC : nR)) {
+                    const T v = row ? fb.S[(long long)x * nC + y] : fb.St[(long long)(x - nR) * nR + y];
+                    k = line_key(v, y);
+                    id = y;
+                }
+            }
+            B.put(e, k, id);
+        }
+        __syncthreads();
+        // merge sizes 2, 4, 8 stay inside groups of 8
+        for (int c = threadIdx.x; c < E / 8; c += kSortThreads)
+            for (int k = 2; k <= (P < 8 ? P : 8); k <<= 1) sort8<T>(B, 8 * c, k, k >> 1, P);
+        __syncthreads();
+        for (int k = 16; k <= P; k <<= 1) {
+            for (int j = k >> 1; j >= 8; j >>= 1) {
+                for (int q = threadIdx.x; q < E / 2; q += kSortThreads) {
+                    const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+                    const int l = i + j;
+                    const bool up = k == P || (i & k) == 0;  // the last merge of a line is ascending
+                    uint64_t ka, kb;
+                    int ia, ib;
+                    B.get(i, ka, ia);
+                    B.get(l, kb, ib);
+                    if (key_gt(ka, ia, kb, ib) == up) {
+                        B.put(i, kb, ib);
+                        B.put(l, ka, ia);
+                    }
+                }
+                __syncthreads();
+            }
+            for (int c = threadIdx.x; c < E / 8; c += kSortThreads) sort8<T>(B, 8 * c, k, 4, P);
+            __syncthreads();
+        }
+        for (int e = threadIdx.x; e < E; e += kSortThreads) {
+            const int x = g * G + (e >> lgP), y = e & (P - 1);
+            if (x < lines) {
+                const bool row = x < nR;
+                if (y < (row ? nC : nR)) {
+                    uint64_t kk;
+                    int ii;
+                    B.get(e, kk, ii);
+                    uint16_t* out = row ? fb.lists + (long long)x * nC
+                                        : fb.lists + (long long)nR * nC + (long long)(x - nR) * nR;
+                    out[y] = (uint16_t)B.index_of(kk, ii);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// First position >= q of a sorted line (n entries) whose partner is free
+// (state -1), and that partner in y; n and -1 if none.  The entries are read
+// W at a time: 8 for the first step (the partner is usually among them), 32
+// (about one cache line) after that, so a long run of taken partners costs
+// few load latencies.
+template <int W>
+__device__ inline int free_in_step(const uint16_t* line, int q, int n, const int* state, int& y) {
+    int v[W];
+#pragma unroll
+    for (int a = 0; a < W; ++a) v[a] = q + a < n ? line[q + a] : 0;
+    int hit = -1;
+#pragma unroll
+    for (int a = W - 1; a >= 0; --a)
+        if (q + a < n && state[v[a]] == -1) hit = a;
+    if (hit >= 0) y = v[hit];
+    return hit;
+}
+
+__device__ inline int first_free(const uint16_t* line, int q, int n, const int* state, int& y) {
+    if (q < n) {
+        const int h = free_in_step<8>(line, q, n, state, y);
+        if (h >= 0) return q + h;
+        q += 8;
+    }
+    while (q < n) {
+        const int h = free_in_step<32>(line, q, n, state, y);
+        if (h >= 0) return q + h;
+        q += 32;
+    }
+    y = -1;
+    return n;
+}
+
+// One workgroup per pair: greedy matching on the sorted lines, margin, outputs
+// (LDS: the state of every line, 8 bytes, within large_finish_lds).
 template <typename T>
 __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -672,7 +927,7 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     __shared__ double red[NW];
     __shared__ int s_count;
     const int p = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = uni(tid / kWave);
+    const int tid = threadIdx.x;
     const LargeState* s = J.st + p;
     cfsim_pair_result* res = J.res + p;
     if (s->status & CFSIM_INVALID_INPUT) {
@@ -681,214 +936,72 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     }
     const int f = s->final_step;
     const bool rz = s->rz != 0;
-    const int nR = rz ? s->M : s->nB;   // rows of S (B side)
-    const int nC = rz ? s->M : s->nA;   // columns of S (A side)
+    const FinalBufs<T> fb = final_bufs<T>(J, p, s);
+    const int nR = fb.nR, nC = fb.nC;
     const long long total = (long long)nR * nC;
-    T* S = rz ? buf_of<T>(J, p, kSlotS) : buf_of<T>(J, p, f & 3);
-    if (f == 0) {
-        const T c0v = T(1.0 / sqrt((double)nR * (double)nC));
-        for (long long o = tid; o < total; o += kFinishThreads) S[o] = c0v;
-    } else if (!rz) {
-        const T sig = T(1.0 / s->nu_k[f & 3]);
-        for (long long o = tid; o < total; o += kFinishThreads) S[o] = S[o] * sig;
-    } else {
-        // state row r (node of the larger graph), expanded column qq; the
-        // state holds S (swap = 0) or S^T (swap = 1)
-        const double sig = 1.0 / s->nu_k[f & 3];
-        const T* U = buf_of<T>(J, p, kSlotU + (f & 3));
-        const int m = s->nC, M = s->M;
-        for (long long o = tid; o < total; o += kFinishThreads) {
-            const int r = (int)(o / M), qq = (int)(o - (long long)r * M);
-            const Interp ip = interp_at(qq, m, M);
-            const T* urow = U + (long long)r * m;
-            double y;
-            if (ip.r1 == ip.r0)
-                y = (double)urow[ip.r0] * sig;
-            else
-                y = (1.0 - ip.f) * ((double)urow[ip.r0] * sig) + ip.f * ((double)urow[ip.r1] * sig);
-            if (s->swap)
-                S[(long long)qq * M + r] = T(y);
-            else
-                S[o] = T(y);
-        }
-    }
-    __syncthreads();
-    // S^T in a free slot, so that a column's candidates are a contiguous line too
-    T* St = rz ? buf_of<T>(J, p, kSlotU + ((f + 1) & 3)) : buf_of<T>(J, p, (f + 1) & 3);
-    for (long long o = tid; o < total; o += kFinishThreads) {
-        const int r = (int)(o / nC), c = (int)(o - (long long)r * nC);
-        St[(long long)c * nR + r] = S[o];
-    }
-    __syncthreads();
-    __threadfence_block();
+    T* S = fb.S;
+    const uint16_t* rl = fb.lists;                       // row r's columns in greedy order
+    const uint16_t* cl = fb.lists + (long long)nR * nC;  // column c's rows in greedy order
 
     // Greedy matching by locally dominant rounds: a free row and a free column
     // that are each other's best free partner are matched (the largest free
-    // entry always is).  A stale best (-2) is recomputed by one wave scanning
-    // the row of S or the row of S^T (contiguous loads, eight per lane in
-    // flight).  The scan keeps each lane's two best free candidates and merges
-    // them into a prefix of the line's order (it stops where a lane's third
-    // candidate, unseen, could come next), cached in a free slot: when the
-    // line's best is taken, its next best free partner is the first cached one
-    // still free (partners are only ever taken, so nothing outside the prefix
-    // can rank before it), and the line is scanned again only when the cached
-    // ones are gone.  Near rank-one S makes every free line stale in every
-    // round; the cache saves most of those scans.  (Tiny pairs whose slot
-    // cannot hold the cache rescan every stale line.)
-    int* cache = (long long)(nR + nC) * kCache * (long long)sizeof(int) <= J.slot_elems * (long long)sizeof(T)
-                     ? reinterpret_cast<int*>(rz ? buf_of<T>(J, p, kSlotU + ((f + 2) & 3)) : buf_of<T>(J, p, (f + 2) & 3))
-                     : nullptr;
+    // entry always is).  A line's best free partner is the first free one in
+    // its sorted order; partners are only ever taken, so each line keeps a
+    // pointer into its order that only moves forward, and its current best in
+    // LDS: only a line whose best was taken reads its order again.
     int* rstate = reinterpret_cast<int*>(smem);
-    int* rbest = rstate + nR;
-    int* cstate = rbest + nR;
-    int* cbest = cstate + nC;
+    int* cstate = rstate + nR;
+    uint16_t* rptr = reinterpret_cast<uint16_t*>(cstate + nC);
+    uint16_t* cptr = rptr + nR;
+    int16_t* rbest = reinterpret_cast<int16_t*>(cptr + nC);   // -1: no free partner left
+    int16_t* cbest = rbest + nR;
     for (int r = tid; r < nR; r += kFinishThreads) {
         rstate[r] = -1;
-        rbest[r] = -2;
+        rptr[r] = 0;
+        rbest[r] = -1;
     }
     for (int c = tid; c < nC; c += kFinishThreads) {
         cstate[c] = -1;
-        cbest[c] = -2;
+        cptr[c] = 0;
+        cbest[c] = -1;
     }
     if (tid == 0) s_count = 0;
     __syncthreads();
     const int need = min(nR, nC);
     int done = 0;
+    bool first = true;
     while (done < need) {
-        for (int it = wave; it < nR + nC; it += NW) {
-            const bool is_row = it < nR;
-            const int x = is_row ? it : it - nR;
-            if (is_row ? (uni(rstate[x]) != -1 || uni(rbest[x]) != -2)
-                       : (uni(cstate[x]) != -1 || uni(cbest[x]) != -2))
-                continue;
-            // candidates: row x of S (free columns) or row x of S^T (free rows)
-            const T* line = is_row ? S + (long long)x * nC : St + (long long)x * nR;
-            const int n = is_row ? nC : nR;
-            const int* other = is_row ? cstate : rstate;
-            const int kb = is_row ? x * nC : x, ks = is_row ? 1 : nC;
-            // numbers first: NaN entries only if no number is left
-            T v1 = T(-__builtin_inf()), v2 = T(-__builtin_inf());
-            int k1 = INT_MAX, k2 = INT_MAX, i1 = -1, i2 = -1;
-            bool nan_seen = false;
-            for (int y0 = lane; y0 < n; y0 += 8 * kWave) {
-                T v[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int y = y0 + u * kWave;
-                    v[u] = y < n ? line[y] : T(-1);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int y = y0 + u * kWave;
-                    if (y < n && other[y] == -1) {
-                        const int key = kb + y * ks;
-                        if (v[u] != v[u]) {
-                            nan_seen = true;
-                        } else if (v[u] > v2 || (v[u] == v2 && key < k2)) {
-                            if (v[u] > v1 || (v[u] == v1 && key < k1)) {
-                                v2 = v1;
-                                k2 = k1;
-                                i2 = i1;
-                                v1 = v[u];
-                                k1 = key;
-                                i1 = y;
-                            } else {
-                                v2 = v[u];
-                                k2 = key;
-                                i2 = y;
-                            }
-                        }
-                    }
-                }
-            }
-            int* cl = cache ? cache + (long long)it * kCache : nullptr;
-            int head = 0, first = -1, got = 0;
-            for (int j = 0; j < kCache; ++j) {
-                if (__ballot(head == 2 && i2 >= 0) != 0) break;  // a lane's unseen third could be next
-                const T ov = head == 0 ? v1 : (head == 1 ? v2 : T(-__builtin_inf()));
-                const int ok = head == 0 ? k1 : (head == 1 ? k2 : INT_MAX);
-                const int oi = head == 0 ? i1 : (head == 1 ? i2 : -1);
-                T bv = ov;
-                int bk = ok, bi = oi;
-                wave_argmax(bv, bk, bi);
-                if (bi < 0) break;                   // no candidate left
-                if (oi == bi && ok == bk) ++head;   // keys are distinct: the one winning lane
-                if (cl && lane == 0) cl[j] = bi;
-                if (j == 0) first = bi;
-                got = j + 1;
-            }
-            if (first < 0 && __ballot(nan_seen) != 0) {
-                // no number left on the line: its free NaN entry with the smallest key
-                T z0v = T(-__builtin_inf());
-                int nk = INT_MAX, ni = -1;
-                for (int y = lane; y < n; y += kWave) {
-                    const int key = kb + y * ks;
-                    if (other[y] == -1 && line[y] != line[y] && key < nk) {
-                        nk = key;
-                        ni = y;
-                    }
-                }
-                if (ni >= 0) z0v = T(0);
-                wave_argmax(z0v, nk, ni);
-                first = ni;
-                if (cl && lane == 0) cl[0] = ni;
-                got = 1;
-            }
-            if (cl && lane == 0)
-                for (int j = got; j < kCache; ++j) cl[j] = -1;
-            if (lane == 0) {
-                if (is_row)
-                    rbest[x] = first;
-                else
-                    cbest[x] = first;
-            }
+        for (int r = tid; r < nR; r += kFinishThreads) {
+            if (rstate[r] != -1) continue;
+            const int b = rbest[r];
+            if (!first && (b < 0 || cstate[b] == -1)) continue;   // still the best free partner (or none left)
+            int y;
+            const int q = first_free(rl + (long long)r * nC, rptr[r], nC, cstate, y);
+            rptr[r] = (uint16_t)q;
+            rbest[r] = (int16_t)y;
         }
+        for (int c = tid; c < nC; c += kFinishThreads) {
+            if (cstate[c] != -1) continue;
+            const int b = cbest[c];
+            if (!first && (b < 0 || rstate[b] == -1)) continue;
+            int y;
+            const int q = first_free(cl + (long long)c * nR, cptr[c], nR, rstate, y);
+            cptr[c] = (uint16_t)q;
+            cbest[c] = (int16_t)y;
+        }
+        first = false;
         __syncthreads();
         for (int r = tid; r < nR; r += kFinishThreads) {
-            if (rstate[r] == -1) {
-                const int c = rbest[r];
-                if (c >= 0 && cbest[c] == r) {
-                    rstate[r] = c;
-                    cstate[c] = r;
-                    atomicAdd(&s_count, 1);
-                }
+            const int c = rbest[r];
+            if (rstate[r] == -1 && c >= 0 && cbest[c] == r) {
+                rstate[r] = c;
+                cstate[c] = r;
+                atomicAdd(&s_count, 1);
             }
         }
         __syncthreads();
-        // stale bests: the next cached free partner, else a new scan (-2)
-        for (int r = tid; r < nR; r += kFinishThreads)
-            if (rstate[r] == -1 && rbest[r] >= 0 && cstate[rbest[r]] != -1) {
-                int nb = -2;
-                if (cache) {
-                    const int* cl = cache + (long long)r * kCache;
-                    for (int q = 0; q < kCache; ++q) {
-                        const int y = cl[q];
-                        if (y >= 0 && cstate[y] == -1) {
-                            nb = y;
-                            break;
-                        }
-                    }
-                }
-                rbest[r] = nb;
-            }
-        for (int c = tid; c < nC; c += kFinishThreads)
-            if (cstate[c] == -1 && cbest[c] >= 0 && rstate[cbest[c]] != -1) {
-                int nb = -2;
-                if (cache) {
-                    const int* cl = cache + (long long)(nR + c) * kCache;
-                    for (int q = 0; q < kCache; ++q) {
-                        const int y = cl[q];
-                        if (y >= 0 && rstate[y] == -1) {
-                            nb = y;
-                            break;
-                        }
-                    }
-                }
-                cbest[c] = nb;
-            }
-        const int now = s_count;
-        __syncthreads();
-        if (now == done) break;  // guard: the earliest free entry is always a mutual best
+        const int now = s_count;  // s_count changes next behind the next round's first barrier
+        if (now == done) break;   // guard: the earliest free entry is always a mutual best
         done = now;
     }
 
@@ -929,13 +1042,42 @@ int large_step_grid(int num_cus) { return num_cus * 8; }
 
 size_t large_finish_lds(int max_nodes) { return (size_t)16 * (size_t)max_nodes; }
 
+// Sort workspace in LDS: G * P keys (8 bytes) and, for FP64, indices (4 bytes).
+size_t large_sort_lds(int max_nodes, int esize) {
+    const int P = pow2_at_least(max_nodes);
+    return (size_t)(P > kSortElems ? P : kSortElems) * (esize == 8 ? 12 : 8);
+}
+
 int set_large_attributes() {
     int e = 0;
     e |= (int)hipFuncSetAttribute(reinterpret_cast<const void*>(&large_finish<float>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     e |= (int)hipFuncSetAttribute(reinterpret_cast<const void*>(&large_finish<double>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    e |= (int)hipFuncSetAttribute(reinterpret_cast<const void*>(&large_sort_lines<float>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_sort_lds(kLargeMaxNodes, 4));
+    e |= (int)hipFuncSetAttribute(reinterpret_cast<const void*>(&large_sort_lines<double>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)large_sort_lds(kLargeMaxNodes, 8));
     return e;
+}
+
+// The three kernels after the last update.  Workgroups per pair: the 32 x 32
+// tiles or line groups of the largest pair, at most 64.
+template <typename T>
+static int launch_finish(const LargeJob& J, hipStream_t stream) {
+    const int tiles = ((J.max_nodes + 31) / 32) * ((J.max_nodes + 31) / 32);
+    const int P = pow2_at_least(J.max_nodes);
+    const int G = P >= kSortElems ? 1 : kSortElems / P;
+    const int groups = (2 * J.max_nodes + G - 1) / G;
+    hipLaunchKernelGGL(large_final<T>, dim3(tiles < 64 ? tiles : 64, J.n_pairs), dim3(kFinalThreads), 0, stream, J);
+    int e = (int)hipGetLastError();
+    if (e != 0) return e;
+    hipLaunchKernelGGL(large_sort_lines<T>, dim3(groups < 64 ? groups : 64, J.n_pairs), dim3(kSortThreads),
+                       large_sort_lds(J.max_nodes, (int)sizeof(T)), stream, J);
+    if ((e = (int)hipGetLastError()) != 0) return e;
+    hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), large_finish_lds(J.max_nodes), stream,
+                       J);
+    return (int)hipGetLastError();
 }
 
 template <typename T>
@@ -954,9 +1096,7 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
             hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
         }
-        const size_t lds = large_finish_lds(J.max_nodes);
-        hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
-        return (int)hipGetLastError();
+        return launch_finish<T>(J, stream);
     }
     if (J.resize) {
         hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, 0);
@@ -972,9 +1112,7 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
         hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
         if ((e = (int)hipGetLastError()) != 0) return e;
     }
-    const size_t lds = large_finish_lds(J.max_nodes);
-    hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), lds, stream, J);
-    return (int)hipGetLastError();
+    return launch_finish<T>(J, stream);
 }
 
 int launch_large(int dtype, const LargeJob& J, int grid, hipStream_t stream) {
