@@ -273,7 +273,7 @@ def workload_legs(ctx, stream, reps=3):
     """The other hot-path rows, each on its own synthetic workload: the plain
     12 x 16 pair, large pairs (tiled path), query-vs-database with top-16,
     the reverse mode, the scale-to-common-size mode of the all-pairs batch,
-    and the elementwise distances of Table 1.  Inputs resident in HBM; every time is the average of `reps` timed
+    the elementwise distances of Table 1 and the damped IsoRank measure.  Inputs resident in HBM; every time is the average of `reps` timed
     calls after one warm-up; every leg states its error against the FP64 GPU
     path (itself parity-tested against the CPU oracle)."""
     import torch
@@ -446,6 +446,38 @@ def workload_legs(ctx, stream, reps=3):
                          all_finite=bool(torch.isfinite(d).all()))
         del gs, d
     out["distances"] = dist
+
+    # f2: damped IsoRank (alpha = 0.85, uniform prior) of every pair of the
+    # 256-CFG batch, FP32 against the FP64 GPU path.  Work per update: the
+    # gather over Z = x / d (4 nnz_A nnz_B flops) and per entry the division
+    # by d, the damped update, the 1-norm change and the squared norm (7 flops).
+    w = config_graphs(1)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, want_S=True, path="damped",
+                 alpha=0.85)
+    b.run()
+    torch.cuda.synchronize()
+    ms = _time_ms(b.run, reps, stream)
+    b64 = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f64", want_match=True, want_S=True, path="damped",
+                   alpha=0.85)
+    b64.run()
+    torch.cuda.synchronize()
+    r32, r64 = b.results(), b64.results()
+    errs = err_summary(*seg_errors(b.S, b64.S, b.nA * b.nB))
+    nnz = np.diff(gs.edge_off).astype(np.float64)
+    ea, eb = nnz[w["pair_a"]], nnz[w["pair_b"]]
+    flops = float(np.sum(r32["iters"].astype(np.float64) * (4.0 * ea * eb + 7.0 * b.nA * b.nB)))
+    tf = flops / (ms * 1e-3) / 1e12
+    out["damped"] = dict(workload="all 32,640 pairs of the 256-CFG batch, damped IsoRank alpha = 0.85, uniform "
+                                  "prior, FP32, tol 1e-12 on the 1-norm step, <=200 updates",
+                         ms_per_call=ms, pairs_per_s=len(w["pair_a"]) / (ms * 1e-3),
+                         alu_roofline=dict(bound="alu", achieved=tf, peak=157.3, unit="TFLOP/s", frac=tf / 157.3),
+                         iters_fp64_median=float(np.median(r64["iters"])),
+                         near_tie_count=int(np.sum((r32["status"] & cf.NEAR_TIE) != 0)),
+                         matchings_equal_fp32_fp64=int(sum(np.array_equal(x, y) for x, y in
+                                                           zip(b.matches(), b64.matches()))),
+                         **errs)
+    del b, b64, gs
     return out
 
 
@@ -454,7 +486,8 @@ def profile_only(spec: str):
       pair:NA:NB:DTYPE:MAX_ITER:REPS  the plain path on one seeded pair
                                       (tol 0: every launch runs MAX_ITER updates)
       workload:NAME:REPS              NAME = batch, large, largemfma, resize,
-                                      query, backward or fp64final (FP32), or
+                                      query, backward, fp64final or damped
+                                      (FP32), or
                                       distances / distlarge (the elementwise
                                       distances of the batch / the large pairs,
                                       FP64); REPS calls after one warm-up"""
@@ -473,7 +506,7 @@ def profile_only(spec: str):
     elif f[0] == "workload" and len(f) == 3:
         name, reps = f[1], int(f[2])
         idx = {"batch": 1, "resize": 1, "fp64final": 1, "large": 2, "largemfma": 2, "backward": 3,
-               "query": 4, "distances": 1, "distlarge": 2}.get(name)
+               "query": 4, "distances": 1, "distlarge": 2, "damped": 1}.get(name)
         if idx is None:
             raise SystemExit(f"unknown workload {name!r}")
         if name in ("distances", "distlarge"):
@@ -491,6 +524,7 @@ def profile_only(spec: str):
         kw.update(dict(mfma=True) if name == "largemfma" else {})
         kw.update(dict(resize="bilinear") if name == "resize" else {})
         kw.update(dict(fp64_final=True) if name == "fp64final" else {})
+        kw.update(dict(path="damped", alpha=0.85) if name == "damped" else {})
         gs = cfm.pack(ctx, w["graphs"])
         b = cfm.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, **kw)
         gsc = torch.ones(b.n_pairs, dtype=torch.float64, device=gs.w.device)

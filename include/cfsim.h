@@ -386,6 +386,40 @@ cfsim_status cfsim_score_batch_ckpt(cfsim_context* ctx, const cfsim_graph_set* s
                                     int32_t checkpoint_every, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The damped IsoRank measure of many pairs: Table 1, row "Iso", in its full
+ * form (I - alpha Q x P) x = (1 - alpha) E, with IsoRank's normalisation of
+ * the product-graph operator (Section 4.2, Pairwise Comparison; Table 1).
+ * For pair p (A = graph pair_a[p], B = graph pair_b[p] of `set`):
+ *   M = B (x) A + B^T (x) A^T on the row-major vec of X (n_B x n_A), the
+ *   operator of the undamped measure; M_hat = M D^-1 with D the column sums
+ *   of M, d_uv = c^B_u c^A_v + r^B_u r^A_v (c: column sums, r: row sums of
+ *   the transition matrices), a zero column staying zero;
+ *   E = the uniform 1/(n_A n_B) (prior = NULL), or pair p's prior
+ *   (n_B x n_A row-major FP64 at prior + prior_off[p], device memory,
+ *   finite and non-negative with a positive sum) divided by its sum;
+ *   x_0 = E, x_k = alpha M_hat x_{k-1} + (1 - alpha) E, stopped at the first
+ *   k with delta = ||x_k - x_{k-1}||_1 < opt->tol or at k = opt->max_iter
+ *   (the update contracts by alpha in the 1-norm, so ||x_k - x*||_1 <=
+ *   alpha delta / (1 - alpha) for the solution x*);
+ *   S = x_k / ||x_k||_F; greedy matching, score and margin as for the
+ *   undamped measure (see the top of this file).
+ * res[p]: score, nu = ||x_k||_F, delta, margin, iters = k, status
+ * (CONVERGED or HIT_MAX_ITER, NEAR_TIE, FP64_FINAL; INVALID_INPUT for a bad
+ * index, a pair no kernel holds, or a prior that is negative, non-finite or
+ * all zero).  0 <= alpha < 1 (alpha = 0 returns the prior).  Same buffers,
+ * workspace (cfsim_batch_workspace_size), schedule, kernels' shapes and
+ * CFSIM_FLAG_FP64_FINAL pass as cfsim_score_batch, whose pairs the damped
+ * kernels take bucket by bucket.  Errors as cfsim_score_batch, plus
+ * CFSIM_E_INVALID_ARG for alpha outside [0, 1) or only one of prior /
+ * prior_off given, and CFSIM_E_UNSUPPORTED with resize.
+ */
+cfsim_status cfsim_score_damped(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, double alpha,
+                                const double* prior, const int64_t* prior_off, cfsim_pair_result* res,
+                                int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Step a11 - ranking of a query against a database: the k best scores.
  * scores[i * stride] for i in [0, n) (device; stride 4 reads the score field
  * of a cfsim_pair_result array).  Larger score first, ties to the lower

@@ -103,6 +103,8 @@ SIGNATURES = {
     "cfsim_context_get_tune": (ctypes.c_int, [_P, _I32, _P, _I32]),
     "cfsim_topk_workspace_size": (_SZ, [_I64, _I32]),
     "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
+    "cfsim_score_damped": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
+                                          ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "cfsim_distances_workspace_size": (_SZ, [ctypes.POINTER(GraphSetC), _I64]),
     "cfsim_distances": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.c_double, _P, _P, _SZ,
                                        _P]),
@@ -345,10 +347,14 @@ class Batch:
 
     def __init__(self, ctx: Context, gs: GraphSet, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12,
                  resize="none", want_match=True, want_S=False, w: torch.Tensor | None = None, path="batch",
-                 tie_tol=0.0, fp64_final=False, mfma=False, checkpoint_every=0):
-        if path not in ("batch", "large"):
-            raise ValueError("path must be 'batch' (cfsim_score_batch) or 'large' (cfsim_score_large)")
+                 tie_tol=0.0, fp64_final=False, mfma=False, checkpoint_every=0, alpha=None, prior=None):
+        if path not in ("batch", "large", "damped"):
+            raise ValueError("path must be 'batch' (cfsim_score_batch), 'large' (cfsim_score_large) "
+                             "or 'damped' (cfsim_score_damped)")
+        if (path == "damped") != (alpha is not None):
+            raise ValueError("alpha is given exactly for the damped path")
         self.path = path
+        self.alpha = None if alpha is None else float(alpha)
         self.ctx, self.gs = ctx, gs
         self.opt = options(dtype, max_iter, tol, resize, tie_tol, fp64_final, mfma)
         dev = gs.w.device
@@ -390,9 +396,24 @@ class Batch:
             off = np.concatenate([[0], np.cumsum(per)]).astype(np.int64)
             self.ckpt_off = torch.as_tensor(off[:-1]).to(dev)
             self.ckpt = torch.empty(max(int(off[-1]), 1), dtype=_torch_dtype(self.opt), device=dev)
+        # damped path: the caller's priors, one n_B x n_A FP64 array per pair
+        # (None: uniform), packed with their element offsets
+        self.prior = self.prior_off = None
+        if prior is not None:
+            if path != "damped":
+                raise ValueError("a prior is taken by the damped path only")
+            if len(prior) != self.n_pairs:
+                raise ValueError("one prior per pair")
+            flat = [np.asarray(x, np.float64).reshape(-1) for x in prior]
+            for x, a, b in zip(flat, nA, nB):
+                if x.size != a * b:
+                    raise ValueError("prior p must hold n_B x n_A entries")
+            off = np.concatenate([[0], np.cumsum([x.size for x in flat])]).astype(np.int64)
+            self.prior_off = torch.as_tensor(off[:-1]).to(dev)
+            self.prior = torch.as_tensor(np.concatenate(flat) if flat else np.zeros(1)).to(dev)
         self.w = w
         self.set_c = gs.c_struct(w)
-        size_fn = lib().cfsim_batch_workspace_size if path == "batch" else lib().cfsim_large_workspace_size
+        size_fn = lib().cfsim_large_workspace_size if path == "large" else lib().cfsim_batch_workspace_size
         self.ws_bytes = size_fn(ctx.handle, ctypes.byref(self.set_c), self.n_pairs, ctypes.byref(self.opt))
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=dev)
 
@@ -402,6 +423,13 @@ class Batch:
                 self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a), _ptr(self.pair_b), self.n_pairs,
                 ctypes.byref(self.opt), _ptr(self.res), _ptr(self.match), _ptr(self.match_off), _ptr(self.S),
                 _ptr(self.S_off), _ptr(self.ckpt), _ptr(self.ckpt_off), self.checkpoint_every, _ptr(self.ws),
+                self.ws_bytes, _stream(stream)))
+            return
+        if self.path == "damped":
+            _check(lib().cfsim_score_damped(
+                self.ctx.handle, ctypes.byref(self.set_c), _ptr(self.pair_a), _ptr(self.pair_b), self.n_pairs,
+                ctypes.byref(self.opt), self.alpha, _ptr(self.prior), _ptr(self.prior_off), _ptr(self.res),
+                _ptr(self.match), _ptr(self.match_off), _ptr(self.S), _ptr(self.S_off), _ptr(self.ws),
                 self.ws_bytes, _stream(stream)))
             return
         fn = lib().cfsim_score_batch if self.path == "batch" else lib().cfsim_score_large
@@ -540,6 +568,18 @@ def score_batch(ctx, gs, pair_a, pair_b, dtype="f32", max_iter=200, tol=1e-12, r
     """Batched (or large-pair) path: run once, synchronise, return (results, matches, S list)."""
     b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, resize, want_match, want_S, path=path,
               tie_tol=tie_tol, fp64_final=fp64_final)
+    b.run()
+    torch.cuda.synchronize()
+    return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)
+
+
+def score_damped(ctx, gs, pair_a, pair_b, alpha=0.85, prior=None, dtype="f32", max_iter=200, tol=1e-12,
+                 want_match=True, want_S=False, tie_tol=0.0, fp64_final=False):
+    """Damped IsoRank of every pair (cfsim_score_damped): run once, synchronise,
+    return (results, matches, S list).  prior: None (uniform) or one n_B x n_A
+    array per pair."""
+    b = Batch(ctx, gs, pair_a, pair_b, dtype, max_iter, tol, "none", want_match, want_S, path="damped",
+              tie_tol=tie_tol, fp64_final=fp64_final, alpha=alpha, prior=prior)
     b.run()
     torch.cuda.synchronize()
     return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)

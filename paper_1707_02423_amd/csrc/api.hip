@@ -681,10 +681,19 @@ struct CkptOut {
     int every;
 };
 
+// The damped measure of cfsim_score_damped (on = 0: the undamped iteration).
+struct Damping {
+    int on;
+    double alpha;
+    const double* prior;
+    const int64_t* prior_off;
+};
+
 static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a, const int32_t* pair_b,
                         int64_t n_pairs, const cfsim_options* opt, int dtype, const cfsim_pair_result* filter,
                         cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
-                        const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed, const CkptOut& ck) {
+                        const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed, const CkptOut& ck,
+                        const Damping& dm) {
     const int esize = esize_of(dtype);
     cfsim::PlanJob plan{};
     plan.set = ref_of(set);
@@ -718,6 +727,10 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     job.ckpt = ck.ptr;
     job.ckpt_off = ck.off;
     job.ckpt_every = ck.every;
+    job.damped = dm.on;
+    job.alpha = dm.alpha;
+    job.prior = dm.prior;
+    job.prior_off = dm.prior_off;
     const int d = dtype_index(dtype);
     // The bucket kernels run one after another on the caller's stream, each
     // with the whole device: a bucket's persistent grid drains its queue
@@ -748,16 +761,16 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
 static int enqueue_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                          const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
                          int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
-                         hipStream_t st, bool timed, const CkptOut& ck) {
+                         hipStream_t st, bool timed, const CkptOut& ck, const Damping& dm) {
     const int esize = fp64_final(opt) ? 8 : esize_of(opt->dtype);
     const BatchWs b = carve_batch(ctx, ws, n_pairs, esize, set->max_nodes);
     int e = enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, opt->dtype, nullptr, res, match, match_off, S_out,
-                         S_off, b, st, timed, ck);
+                         S_off, b, st, timed, ck, dm);
     if (e != 0 || !fp64_final(opt)) return e;
     // FP64 pass over the pairs whose FP32 result is a near tie (the schedule
     // arrays are reused: the stream orders the passes)
     return enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, CFSIM_F64, res, res, match, match_off, S_out, S_off, b,
-                        st, false, CkptOut{nullptr, nullptr, 0});
+                        st, false, CkptOut{nullptr, nullptr, 0}, dm);
 }
 
 static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -791,7 +804,8 @@ static cfsim_status run_large(cfsim_context* ctx, const cfsim_graph_set* set, co
 static cfsim_status score_batch(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                                 const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
                                 cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
-                                const int64_t* S_off, const CkptOut& ck, void* ws, size_t ws_bytes, void* stream) {
+                                const int64_t* S_off, const CkptOut& ck, const Damping& dm, void* ws,
+                                size_t ws_bytes, void* stream) {
     cfsim_status s;
     if ((s = check_set(set)) != CFSIM_OK) return s;
     if ((s = check_options(opt)) != CFSIM_OK) return s;
@@ -822,7 +836,7 @@ static cfsim_status score_batch(cfsim_context* ctx, const cfsim_graph_set* set, 
     }
     if (ctx->timing || graphs_disabled()) {
         e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st,
-                          ctx->timing != 0, ck);
+                          ctx->timing != 0, ck, dm);
         if (e != 0) return hip_fail(e, "batch launch");
         if (ctx->timing) ctx->timed = 1;
         return ok();
@@ -831,9 +845,13 @@ static cfsim_status score_batch(cfsim_context* ctx, const cfsim_graph_set* set, 
     append_key(key, ck.ptr);
     append_key(key, ck.off);
     append_key(key, ck.every);
+    append_key(key, dm.on);
+    append_key(key, dm.alpha);
+    append_key(key, dm.prior);
+    append_key(key, dm.prior_off);
     return replay_or_capture(ctx, &ctx->graph, &ctx->exec, &ctx->key, key, st, [&](hipStream_t cs) {
         return enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, cs,
-                             false, ck);
+                             false, ck, dm);
     });
 }
 
@@ -842,7 +860,21 @@ cfsim_status cfsim_score_batch(cfsim_context* ctx, const cfsim_graph_set* set, c
                                cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
                                const int64_t* S_off, void* ws, size_t ws_bytes, void* stream) {
     return score_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
-                       CkptOut{nullptr, nullptr, 0}, ws, ws_bytes, stream);
+                       CkptOut{nullptr, nullptr, 0}, Damping{0, 0.0, nullptr, nullptr}, ws, ws_bytes, stream);
+}
+
+cfsim_status cfsim_score_damped(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                                const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, double alpha,
+                                const double* prior, const int64_t* prior_off, cfsim_pair_result* res,
+                                int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                                size_t ws_bytes, void* stream) {
+    if (!(alpha >= 0.0 && alpha < 1.0)) return fail(CFSIM_E_INVALID_ARG, "alpha must lie in [0, 1)");
+    if ((prior == nullptr) != (prior_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "prior and prior_off must both be given or both be NULL");
+    if (opt && opt->resize != CFSIM_RESIZE_NONE)
+        return fail(CFSIM_E_UNSUPPORTED, "the damped measure runs on the unscaled operator only");
+    return score_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
+                       CkptOut{nullptr, nullptr, 0}, Damping{1, alpha, prior, prior_off}, ws, ws_bytes, stream);
 }
 
 cfsim_status cfsim_score_batch_ckpt(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
@@ -857,7 +889,8 @@ cfsim_status cfsim_score_batch_ckpt(cfsim_context* ctx, const cfsim_graph_set* s
     if (opt && fp64_final(opt))
         return fail(CFSIM_E_UNSUPPORTED, "forward checkpoints with CFSIM_FLAG_FP64_FINAL");
     return score_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off,
-                       CkptOut{ckpt, ckpt_off, checkpoint_every}, ws, ws_bytes, stream);
+                       CkptOut{ckpt, ckpt_off, checkpoint_every}, Damping{0, 0.0, nullptr, nullptr}, ws, ws_bytes,
+                       stream);
 }
 
 cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,

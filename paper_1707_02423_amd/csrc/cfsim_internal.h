@@ -193,6 +193,14 @@ struct PairJob {
     void* ckpt;
     const int64_t* ckpt_off;
     int ckpt_every;
+    // Damped measure (damped = 1): the fixed point of x = alpha M_hat x +
+    // (1 - alpha) E with M_hat the operator with unit column sums and E the
+    // prior (NULL: uniform; else pair p's n_B x n_A FP64 prior at
+    // prior + prior_off[p], scaled to unit sum on the device)
+    int damped;
+    double alpha;
+    const double* prior;
+    const int64_t* prior_off;
 };
 
 // Plan: assign every pair a bucket and order each bucket longest first.

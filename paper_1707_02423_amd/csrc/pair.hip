@@ -422,6 +422,234 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
     return out;
 }
 
+// ---------------------------------------------------------------- damped measure
+// Table 1's "Iso" row in its full form, (I - alpha Q x P) x = (1 - alpha) E,
+// read with IsoRank's normalisation: M_hat = M D^-1, D the column sums of the
+// coupled operator M = B (x) A + B^T (x) A^T, and a prior E of unit sum.
+// Column (u, v) of M sums to
+//   d_uv = c^B_u c^A_v + r^B_u r^A_v   (c: column sums, r: row sums),
+// so M_hat x = M (x / d) entry by entry: the update is the undamped gather,
+// run over Z = x / d.  The two buffers hold Z_k (x_k itself where d = 0: such
+// an entry heads a zero column of M and no update reads it with a non-zero
+// weight), and an update of entry (i, j) is
+//   x_{k+1} = alpha (M Z_k)_ij + (1 - alpha) E_ij,   Z_{k+1} = x_{k+1} / d_ij,
+// with x_k = Z_k d_ij (one rounding away) for the stopping test.  Per update,
+// in FP64 and a fixed order: delta = ||x_{k+1} - x_k||_1 and ||x_{k+1}||_F^2.
+// The iteration contracts by alpha in the 1-norm; it stops at the first
+// delta < tol or at max_iter, and S = x / ||x||_F is what the matching reads.
+
+struct DampedSums {
+    double d1, n2;
+};
+
+// Block reduction of both sums (red holds 2 * NW doubles); one barrier.
+template <int NW>
+__device__ inline DampedSums block_sum_damped(DampedSums s, double* red) {
+    s.d1 = wave_sum(s.d1);
+    s.n2 = wave_sum(s.n2);
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[threadIdx.x / kWave] = s.d1;
+        red[NW + threadIdx.x / kWave] = s.n2;
+    }
+    __syncthreads();
+    DampedSums t{0.0, 0.0};
+    for (int w = 0; w < NW; ++w) {
+        t.d1 += red[w];
+        t.n2 += red[NW + w];
+    }
+    return t;
+}
+
+// The prior of a pair: E[i * si + c * sc] * scale for stored entry (i, c),
+// or the uniform 1 / (n_A n_B) (= scale) when E is NULL.
+struct DampedPrior {
+    const double* E;
+    long long si, sc;
+    double scale;
+};
+
+// Row and column sums of the R node of stored row i, from the staged lists.
+template <typename T>
+__device__ inline void row_node_sums(const Lists<T>& G, int i, int ns, int np, T& r, T& c) {
+    const int2 st = G.rstart[i];
+    T a = T(0), b = T(0);
+    for (int q = 0; q < ns; ++q) a += G.sedge[st.x + q].w;
+    for (int q = 0; q < np; ++q) b += G.pedge[st.y + q].w;
+    r = a;
+    c = b;
+}
+
+// Lanes of NCH consecutive 64-column chunks starting at chunk ch0: neighbour
+// lists, columns and the row and column sums of each lane's C node.
+template <typename T, int NCH>
+struct DampedLanes {
+    LaneList<T> L[NCH];
+    int col[NCH];
+    bool cv[NCH];
+    uint64_t ovf[NCH];
+    bool any_ovf;
+    T cr[NCH], cc[NCH];
+};
+
+template <typename T, int NCH>
+__device__ inline void damped_lanes(const Lists<T>& G, int ch0, int nC, DampedLanes<T, NCH>& c) {
+    c.any_ovf = false;
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
+        lane_setup(G, ch0 + q, nC, c.L[q], c.col[q], c.cv[q], c.ovf[q]);
+        c.any_ovf |= c.ovf[q] != 0;
+        T a = T(0), b = T(0);
+        if (c.cv[q]) {
+            const int4 ci = G.cinfo[c.col[q]];
+            for (int t = ci.x; t < ci.y; ++t) a += G.csedge[t].w;
+            for (int t = ci.z; t < ci.w; ++t) b += G.cpedge[t].w;
+        }
+        c.cr[q] = a;
+        c.cc[q] = b;
+    }
+}
+
+template <typename T>
+__device__ inline T prior_at(const DampedPrior& P, int i, int c) {
+    return P.E ? T(P.E[(long long)i * P.si + (long long)c * P.sc] * P.scale) : T(P.scale);
+}
+
+// Passes over the entries of the wave's rows in the chunks of `c`:
+// PASS 0: Z_0 = E / d into Zn;  PASS 1: one update Zc -> Zn with the sums;
+// PASS 2: S = Z d * inv in place in Zn (the final buffer).
+template <int PASS, typename T, int NCH>
+__device__ __forceinline__ void damped_pass(const unsigned char* Zc, unsigned char* Zn, int rowb, int nR, int NW,
+                                            const Lists<T>& G, const DampedLanes<T, NCH>& c, int ch0, T alpha,
+                                            T omega, const DampedPrior& P, T inv, DampedSums& s) {
+    const int wave = uni((int)threadIdx.x / kWave);
+    for (int i = wave; i < nR; i += NW) {
+        const RowRec<T> rr = G.rec[i];
+        T rs, cs;
+        row_node_sums(G, i, uni(rr.ns), uni(rr.np), rs, cs);
+        T y[NCH];
+        if constexpr (PASS == 1) update_row<T, NCH>(Zc, rowb, i, rr, G, c.L, c.ovf, c.any_ovf, c.col, c.cv, y, ch0);
+        const T* zc = reinterpret_cast<const T*>(Zc + (long long)i * rowb);
+        T* zn = reinterpret_cast<T*>(Zn + (long long)i * rowb);
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            if (!c.cv[q]) continue;
+            const int j = c.col[q];
+            const T d = fma_t(cs, c.cc[q], rs * c.cr[q]);
+            if constexpr (PASS == 0) {
+                const T e = prior_at<T>(P, i, j);
+                zn[j] = d > T(0) ? e / d : e;
+            } else if constexpr (PASS == 1) {
+                const T zo = zc[j];
+                const T xo = d > T(0) ? zo * d : zo;
+                const T xn = fma_t(alpha, y[q], omega * prior_at<T>(P, i, j));
+                s.d1 += fabs((double)xn - (double)xo);
+                s.n2 += (double)xn * (double)xn;
+                zn[j] = d > T(0) ? xn / d : xn;
+            } else {
+                const T z = zn[j];
+                zn[j] = (d > T(0) ? z * d : z) * inv;
+            }
+        }
+    }
+}
+
+// The damped iteration of one pair; B0, B1 are the two iterate buffers (LDS,
+// or a global-memory slot when GLOBAL, chunk by chunk as in iterate_global).
+// Returns the buffer holding S = x / ||x||_F.
+template <typename T, int NT, int NCH, bool GLOBAL>
+__device__ __forceinline__ IterOut iterate_damped(const PairJob& J, const PairShape& sh, const Lists<T>& G,
+                                                  unsigned char* B0, unsigned char* B1, const DampedPrior& P,
+                                                  double* red) {
+    constexpr int NW = NT / kWave;
+    const int nR = sh.nR, nC = sh.nC;
+    const int rowb = nC * (int)sizeof(T);
+    const T alpha = T(J.alpha), omega = T(1.0 - J.alpha);
+    IterOut out{0.0, __builtin_inf(), 0, 0u, 0};
+    unsigned char* Zc = B0;
+    unsigned char* Zn = B1;
+    int cur = 0;
+    DampedSums s{0.0, 0.0};
+    DampedLanes<T, NCH> lanes;
+    if constexpr (!GLOBAL) damped_lanes<T, NCH>(G, 0, nC, lanes);
+    auto each_chunk = [&](auto&& f) {
+        if constexpr (GLOBAL) {
+            for (int ch = 0; ch < sh.nchunk; ++ch) {
+                damped_lanes<T, NCH>(G, ch, nC, lanes);
+                f(ch);
+            }
+        } else {
+            f(0);
+        }
+    };
+    each_chunk([&](int ch0) {  // Z_0 = E / d into the first buffer
+        damped_pass<0, T, NCH>(nullptr, Zc, rowb, nR, NW, G, lanes, ch0, alpha, omega, P, T(1), s);
+    });
+    __syncthreads();
+    double n2 = 0.0;
+    for (int k = 1; k <= J.max_iter; ++k) {
+        s = DampedSums{0.0, 0.0};
+        each_chunk([&](int ch0) {
+            damped_pass<1, T, NCH>(Zc, Zn, rowb, nR, NW, G, lanes, ch0, alpha, omega, P, T(1), s);
+        });
+        // the two reductions of consecutive updates use disjoint slots
+        s = block_sum_damped<NW>(s, red + ((k & 1) ? 0 : 2 * NW));
+        unsigned char* t = Zc;
+        Zc = Zn;
+        Zn = t;
+        cur ^= 1;
+        out.iters = k;
+        out.delta = s.d1;
+        n2 = s.n2;
+        if (s.d1 < J.tol) {
+            out.status = CFSIM_CONVERGED;
+            break;
+        }
+    }
+    if (out.status == 0) out.status = CFSIM_HIT_MAX_ITER;
+    if (!(n2 > 0.0) || !isfinite(n2)) {  // only with max_iter updates of a non-finite prior
+        out.status = CFSIM_DEGENERATE;
+        n2 = 1.0;
+    }
+    out.nu = sqrt(n2);
+    const T inv = T(1.0 / out.nu);
+    each_chunk([&](int ch0) {
+        damped_pass<2, T, NCH>(Zc, Zc, rowb, nR, NW, G, lanes, ch0, alpha, omega, P, inv, s);
+    });
+    __syncthreads();
+    out.final_buf = cur;
+    return out;
+}
+
+// Prior of pair p (uniform when the call has none).  A caller's prior must
+// be finite and non-negative with a positive sum, else the pair is invalid
+// (false, the same in every thread).
+template <typename T, int NT>
+__device__ inline bool damped_prior(const PairJob& J, int p, int nA, int nB, const PairShape& sh, DampedPrior& P,
+                                    double* red) {
+    constexpr int NW = NT / kWave;
+    P.E = nullptr;
+    P.scale = 1.0 / ((double)nA * (double)nB);
+    // stored entry (i, c) is S[i][c], or S[c][i] when the pair is stored transposed
+    P.si = sh.swap ? 1 : nA;
+    P.sc = sh.swap ? nA : 1;
+    if (!J.prior) return true;
+    const double* E = J.prior + (J.single ? 0 : J.prior_off[p]);
+    const long long total = (long long)nA * nB;
+    double part = 0.0;
+    int bad = 0;
+    for (long long t = threadIdx.x; t < total; t += NT) {
+        const double v = E[t];
+        bad |= !(v >= 0.0) || !isfinite(v);
+        part += v;
+    }
+    if (__syncthreads_or(bad)) return false;
+    const double sum = block_sum<NW>(part, red);
+    if (!(sum > 0.0) || !isfinite(sum)) return false;
+    P.E = E;
+    P.scale = 1.0 / sum;
+    return true;
+}
+
 // Step a7, rows of at most kSortCols entries: the greedy order itself.  Each
 // stored row's columns are sorted once in that order (bitonic network, one
 // wave per row, 64 * E slots); then one wave repeats: the earliest entry among
@@ -875,7 +1103,7 @@ __device__ inline bool refine_skips(const PairJob& J, int p) {
     return !(st & CFSIM_NEAR_TIE) || (st & CFSIM_INVALID_INPUT);
 }
 
-template <typename T, int NT, int NCHMAX>
+template <typename T, int NT, int NCHMAX, bool DAMPED>
 __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count,
                                          int* s_seg) {
     if (refine_skips(J, p)) return;
@@ -897,6 +1125,20 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
         const Lists<T> G = carve_lists<T>(smem + 2 * sbytes, nR, nC, R.nnz, C.nnz);
         const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
         const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, reinterpret_cast<T*>(smem), s0);
+        if constexpr (DAMPED) {
+            DampedPrior P;
+            if (!damped_prior<T, NT>(J, p, A.n, B.n, sh, P, red)) {
+                if (threadIdx.x == 0) write_invalid(res);
+                return;
+            }
+            unsigned char* B1 = smem + sbytes;
+            if (NCHMAX == 1 || sh.nchunk == 1)
+                it = iterate_damped<T, NT, 1, false>(J, sh, G, smem, B1, P, red);
+            else if (NCHMAX == 2 || sh.nchunk == 2)
+                it = iterate_damped<T, NT, (NCHMAX >= 2 ? 2 : 1), false>(J, sh, G, smem, B1, P, red);
+            else
+                it = iterate_damped<T, NT, NCHMAX, false>(J, sh, G, smem, B1, P, red);
+        } else {
         if constexpr (NT == kWave) order_rows<T, NT>(G, nR, G.rstate, s_seg);  // one wave: no barrier needed
         if (NCHMAX == 1 || sh.nchunk == 1)
             it = iterate_lds<T, NT, 1>(J, smem, sh, sbytes, G, degenerate, red, s_seg, checkpoint_base<T>(J, p));
@@ -905,6 +1147,7 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
                                                            checkpoint_base<T>(J, p));
         else
             it = iterate_lds<T, NT, NCHMAX>(J, smem, sh, sbytes, G, degenerate, red, s_seg, checkpoint_base<T>(J, p));
+        }
     }
     // The pair's graphs, shape and lists again, from fresh reads of the
     // arguments (the same values: the iteration does not change them).
@@ -922,7 +1165,7 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
     match_and_write<T, NT>(Jr, p, A, B, sh, S, St, G, it, res, red, s_count);
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool DAMPED>
 __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
     if (refine_skips(J, p)) return;
     GraphRef A{}, B{};
@@ -943,21 +1186,32 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
     T* S1 = slot + J.slot_elems;
     const T s0 = T(1.0 / sqrt((double)nR * (double)nC));
     const bool degenerate = stage_pair<T, NT>(R, C, nR, nC, G, S0, s0);
-    const IterOut it = iterate_global<T, NT>(J, sh, G, S0, S1, degenerate, red, checkpoint_base<T>(J, p));
+    IterOut it;
+    if constexpr (DAMPED) {
+        DampedPrior P;
+        if (!damped_prior<T, NT>(J, p, A.n, B.n, sh, P, red)) {
+            if (threadIdx.x == 0) write_invalid(res);
+            return;
+        }
+        it = iterate_damped<T, NT, 1, true>(J, sh, G, reinterpret_cast<unsigned char*>(S0),
+                                            reinterpret_cast<unsigned char*>(S1), P, red);
+    } else {
+        it = iterate_global<T, NT>(J, sh, G, S0, S1, degenerate, red, checkpoint_base<T>(J, p));
+    }
     match_and_write<T, NT>(J, p, A, B, sh, it.final_buf ? S1 : S0, it.final_buf ? S0 : S1, G, it, res, red, s_count);
 }
 
 // Persistent driver: one pair at a time per workgroup, pulled from the
 // bucket's queue (or the single pair of the plain path).
-template <bool GLOBAL, typename T, int NT, int NCH>
+template <bool GLOBAL, typename T, int NT, int NCH, bool DAMPED>
 __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count,
                                       int* s_seg) {
     if (J.single) {
         if (blockIdx.x == 0) {
             if constexpr (GLOBAL)
-                global_pair<T, NT>(J, 0, smem, red, s_count);
+                global_pair<T, NT, DAMPED>(J, 0, smem, red, s_count);
             else
-                lds_pair<T, NT, NCH>(J, 0, smem, red, s_count, s_seg);
+                lds_pair<T, NT, NCH, DAMPED>(J, 0, smem, red, s_count, s_seg);
         }
         return;
     }
@@ -969,9 +1223,9 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
         __syncthreads();
         if (item >= Jl.bounds[1]) break;
         if constexpr (GLOBAL)
-            global_pair<T, NT>(Jl, Jl.order[item], smem, red, s_count);
+            global_pair<T, NT, DAMPED>(Jl, Jl.order[item], smem, red, s_count);
         else
-            lds_pair<T, NT, NCH>(Jl, Jl.order[item], smem, red, s_count, s_seg);
+            lds_pair<T, NT, NCH, DAMPED>(Jl, Jl.order[item], smem, red, s_count, s_seg);
     }
 }
 
@@ -988,7 +1242,17 @@ void pair_lds_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (NT / kWave)];
     __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
-    drive<false, T, NT, NCH>(J, smem, red, &s_item, s_count, s_seg);
+    drive<false, T, NT, NCH, false>(J, smem, red, &s_item, s_count, s_seg);
+}
+
+// The damped measure on the same variants and schedule.
+template <typename T, int NT, int NCH>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<NT>())))
+void damped_lds_kernel(PairJob J) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4 * (NT / kWave)];
+    __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
+    drive<false, T, NT, NCH, true>(J, smem, red, &s_item, s_count, s_seg);
 }
 
 template <typename T>
@@ -997,7 +1261,16 @@ void pair_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
     __shared__ int s_item, s_count[2];
-    drive<true, T, kGlobalThreads, 1>(J, smem, red, &s_item, s_count, nullptr);
+    drive<true, T, kGlobalThreads, 1, false>(J, smem, red, &s_item, s_count, nullptr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void damped_global_kernel(PairJob J) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4 * (kGlobalThreads / kWave)];
+    __shared__ int s_item, s_count[2];
+    drive<true, T, kGlobalThreads, 1, true>(J, smem, red, &s_item, s_count, nullptr);
 }
 
 // Pairs no kernel can take get an INVALID_INPUT result.
@@ -1092,30 +1365,36 @@ __global__ __launch_bounds__(256) void buckets_kernel(PlanJob P, int32_t* bucket
 }
 
 template <typename T, int NT, int NCH>
-const void* kernel_ptr() {
-    return reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
+const void* kernel_ptr(bool damped) {
+    return damped ? reinterpret_cast<const void*>(&damped_lds_kernel<T, NT, NCH>)
+                  : reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
+}
+
+template <typename T>
+const void* global_kernel_ptr(bool damped) {
+    return damped ? reinterpret_cast<const void*>(&damped_global_kernel<T>)
+                  : reinterpret_cast<const void*>(&pair_global_kernel<T>);
 }
 
 // Instantiations must match variant_info().
-const void* variant_kernel(int v, int dtype) {
+const void* variant_kernel(int v, int dtype, bool damped = false) {
     if (v == kBucketGlobal)
-        return dtype == CFSIM_F64 ? reinterpret_cast<const void*>(&pair_global_kernel<double>)
-                                  : reinterpret_cast<const void*>(&pair_global_kernel<float>);
+        return dtype == CFSIM_F64 ? global_kernel_ptr<double>(damped) : global_kernel_ptr<float>(damped);
     if (dtype == CFSIM_F64) {
         switch (v) {
-            case 0: return kernel_ptr<double, 64, 1>();
-            case 1: return kernel_ptr<double, 256, 2>();
-            case 2: return kernel_ptr<double, 512, 2>();
-            case 3: return kernel_ptr<double, 1024, 2>();
-            default: return kernel_ptr<double, 1024, 4>();
+            case 0: return kernel_ptr<double, 64, 1>(damped);
+            case 1: return kernel_ptr<double, 256, 2>(damped);
+            case 2: return kernel_ptr<double, 512, 2>(damped);
+            case 3: return kernel_ptr<double, 1024, 2>(damped);
+            default: return kernel_ptr<double, 1024, 4>(damped);
         }
     }
     switch (v) {
-        case 0: return kernel_ptr<float, 64, 2>();
-        case 1: return kernel_ptr<float, 256, 4>();
-        case 2: return kernel_ptr<float, 512, 2>();
-        case 3: return kernel_ptr<float, 1024, 2>();
-        default: return kernel_ptr<float, 1024, 4>();
+        case 0: return kernel_ptr<float, 64, 2>(damped);
+        case 1: return kernel_ptr<float, 256, 4>(damped);
+        case 2: return kernel_ptr<float, 512, 2>(damped);
+        case 3: return kernel_ptr<float, 1024, 2>(damped);
+        default: return kernel_ptr<float, 1024, 4>(damped);
     }
 }
 
@@ -1131,7 +1410,8 @@ int launch_pair_lds(int variant, int dtype, const PairJob& job, int grid, hipStr
     }
     const int esize = dtype == CFSIM_F64 ? 8 : 4;
     void* args[] = {const_cast<PairJob*>(&job)};
-    return (int)hipLaunchKernel(variant_kernel(variant, dtype), dim3(grid), dim3(threads_of(variant, esize)), args,
+    return (int)hipLaunchKernel(variant_kernel(variant, dtype, job.damped != 0), dim3(grid),
+                                dim3(threads_of(variant, esize)), args,
                                 (size_t)lds_of(variant, esize), stream);
 }
 
@@ -1161,12 +1441,13 @@ const char* bucket_kernel_name(int bucket, int dtype) {
 
 int set_kernel_attributes() {
     int e = 0;
-    for (int v = 0; v <= kBucketGlobal; ++v) {
-        e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F32), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      lds_of(v, 4));
-        e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F64), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      lds_of(v, 8));
-    }
+    for (int v = 0; v <= kBucketGlobal; ++v)
+        for (int damped = 0; damped < 2; ++damped) {
+            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F32, damped != 0),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_of(v, 4));
+            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F64, damped != 0),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, lds_of(v, 8));
+        }
     return e;
 }
 

@@ -424,3 +424,23 @@ def test_distances_workspace_bound_covers_every_size():
     large = L.cfsim_distances_workspace_size(ctypes.byref(_set(max_nodes=2048)), 1000)
     assert small >= 1001 * 8 + 1000 * 48 and large >= 1001 * 8 + 1000 * 64 * 48
     assert L.cfsim_distances_workspace_size(ctypes.byref(_set(max_nodes=40000)), 10) == 0
+
+
+@pytest.mark.parametrize("alpha,prior,prior_off,opt_kw,code,text", [
+    (-0.1, None, None, {}, -1, "alpha"),
+    (1.0, None, None, {}, -1, "alpha"),
+    (float("nan"), None, None, {}, -1, "alpha"),
+    (0.85, 0x1000, None, {}, -1, "prior"),
+    (0.85, None, 0x1000, {}, -1, "prior"),
+    (0.85, None, None, dict(resize="bilinear"), -6, "unscaled"),
+    (0.85, None, None, dict(mfma=True), -6, ""),
+    (0.85, None, None, {}, -1, "context"),
+])
+def test_damped_arguments_checked_on_the_host(alpha, prior, prior_off, opt_kw, code, text):
+    L = cf.lib()
+    s = _set()
+    opt = cf.options("f32", **opt_kw)
+    got = L.cfsim_score_damped(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), alpha, prior, prior_off,
+                               0x1000, None, None, None, None, 0x1000, 1 << 40, None)
+    assert got == code
+    assert text in L.cfsim_last_error().decode()
