@@ -273,7 +273,8 @@ def workload_legs(ctx, stream, reps=3):
     """The other hot-path rows, each on its own synthetic workload: the plain
     12 x 16 pair, large pairs (tiled path), query-vs-database with top-16,
     the reverse mode, the scale-to-common-size mode of the all-pairs batch,
-    the elementwise distances of Table 1 and the damped IsoRank measure.  Inputs resident in HBM; every time is the average of `reps` timed
+    the elementwise distances of Table 1, the damped IsoRank measure and the
+    optimal-assignment matching.  Inputs resident in HBM; every time is the average of `reps` timed
     calls after one warm-up; every leg states its error against the FP64 GPU
     path (itself parity-tested against the CPU oracle)."""
     import torch
@@ -478,6 +479,27 @@ def workload_legs(ctx, stream, reps=3):
                                                            zip(b.matches(), b64.matches()))),
                          **errs)
     del b, b64, gs
+
+    # f3: optimal-assignment matching of every pair's FP32 S of the 256-CFG
+    # batch (the batched path's S_out), against the greedy matching's score
+    w = config_graphs(1)
+    gs = cf.pack(ctx, w["graphs"])
+    b = cf.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, want_S=True)
+    b.run()
+    b.assign()
+    torch.cuda.synchronize()
+    ms = _time_ms(b.assign, reps, stream)
+    _, sc = b.assign()
+    torch.cuda.synchronize()
+    sc = sc.cpu().numpy()
+    greedy = b.results()["score"]
+    gain = sc / greedy - 1.0
+    out["assignment"] = dict(workload="optimal assignment (Hungarian, FP64 potentials) of the FP32 S of all 32,640 "
+                                      "pairs of the 256-CFG batch, one wave per matrix",
+                             ms_per_call=ms, pairs_per_s=len(sc) / (ms * 1e-3), all_finite=bool(np.isfinite(sc).all()),
+                             pairs_above_greedy=int(np.sum(gain > 1e-6)), max_gain_over_greedy=float(gain.max()),
+                             mean_gain_over_greedy=float(gain.mean()), min_gain_over_greedy=float(gain.min()))
+    del b, gs
     return out
 
 
@@ -486,8 +508,9 @@ def profile_only(spec: str):
       pair:NA:NB:DTYPE:MAX_ITER:REPS  the plain path on one seeded pair
                                       (tol 0: every launch runs MAX_ITER updates)
       workload:NAME:REPS              NAME = batch, large, largemfma, resize,
-                                      query, backward, fp64final or damped
-                                      (FP32), or
+                                      query, backward, fp64final, damped or
+                                      assign (FP32; assign times cfsim_assign
+                                      on the batch's S), or
                                       distances / distlarge (the elementwise
                                       distances of the batch / the large pairs,
                                       FP64); REPS calls after one warm-up"""
@@ -506,7 +529,7 @@ def profile_only(spec: str):
     elif f[0] == "workload" and len(f) == 3:
         name, reps = f[1], int(f[2])
         idx = {"batch": 1, "resize": 1, "fp64final": 1, "large": 2, "largemfma": 2, "backward": 3,
-               "query": 4, "distances": 1, "distlarge": 2, "damped": 1}.get(name)
+               "query": 4, "distances": 1, "distlarge": 2, "damped": 1, "assign": 1}.get(name)
         if idx is None:
             raise SystemExit(f"unknown workload {name!r}")
         if name in ("distances", "distlarge"):
@@ -525,11 +548,17 @@ def profile_only(spec: str):
         kw.update(dict(resize="bilinear") if name == "resize" else {})
         kw.update(dict(fp64_final=True) if name == "fp64final" else {})
         kw.update(dict(path="damped", alpha=0.85) if name == "damped" else {})
+        kw.update(dict(want_S=True) if name == "assign" else {})
         gs = cfm.pack(ctx, w["graphs"])
         b = cfm.Batch(ctx, gs, w["pair_a"], w["pair_b"], dtype="f32", want_match=True, **kw)
         gsc = torch.ones(b.n_pairs, dtype=torch.float64, device=gs.w.device)
         gw = torch.zeros_like(gs.w)
+        if name == "assign":
+            b.run()
         for _ in range(reps + 1):
+            if name == "assign":
+                b.assign()
+                continue
             b.run()
             if name == "backward":
                 cfm.backward(b, gsc, gw)

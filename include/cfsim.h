@@ -470,6 +470,31 @@ cfsim_status cfsim_distances(cfsim_context* ctx, const cfsim_graph_set* set, con
                              const int32_t* pair_b, int64_t n_pairs, double p, double* out, void* ws,
                              size_t ws_bytes, void* stream);
 
+/*
+ * Optimal-assignment matching of similarity matrices: the other reading of
+ * how the IsoRank solution is reduced to matched node pairs (Section 4.2,
+ * Pairwise Comparison; the paper fixes no extraction rule).  For matrix q
+ * (S of n_rows[q] x n_cols[q], row-major, opt dtype CFSIM_F64 or CFSIM_F32,
+ * at S + S_off[q] elements; e.g. the S_out of cfsim_score_batch or
+ * cfsim_score_damped with its S_off, n_rows = n_B, n_cols = n_A) it finds
+ * the matching of min(n_rows, n_cols) pairs with the largest total sum S_ij
+ * (the linear assignment problem) by the Hungarian method with
+ * shortest augmenting paths and FP64 potentials; ties take the smallest
+ * column index at every step, so the result is deterministic.
+ *   match[match_off[q] + i] = column of row i, or -1 (rows beyond the
+ *   matching when n_rows > n_cols); score[q] = the matched total (FP64).
+ * A matrix with a non-finite entry, or a dimension outside [1, max_dim],
+ * gets score NaN and every row -1.  Device buffers: S, S_off, n_rows,
+ * n_cols, score [n_pairs]; match and match_off may both be NULL.  max_dim
+ * (host) bounds every dimension and sizes the LDS state of a matrix:
+ * 1 <= max_dim <= 4096, else CFSIM_E_INVALID_ARG / CFSIM_E_UNSUPPORTED.
+ * Work per matrix: O(n^2 m) in the worst case, n = min and m = max of its
+ * dimensions.  No workspace.
+ */
+cfsim_status cfsim_assign(cfsim_context* ctx, int32_t dtype, const void* S, const int64_t* S_off,
+                          const int32_t* n_rows, const int32_t* n_cols, int64_t n_pairs, int32_t max_dim,
+                          int32_t* match, const int64_t* match_off, double* score, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -105,6 +105,7 @@ SIGNATURES = {
     "cfsim_topk": (ctypes.c_int, [_P, _P, _I64, _I64, _I32, _P, _P, _P, _SZ, _P]),
     "cfsim_score_damped": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
                                           ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    "cfsim_assign": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
     "cfsim_distances_workspace_size": (_SZ, [ctypes.POINTER(GraphSetC), _I64]),
     "cfsim_distances": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.c_double, _P, _P, _SZ,
                                        _P]),
@@ -458,6 +459,26 @@ class Batch:
         m = self.match.cpu().numpy()
         return [m[o:o + n] for o, n in zip(self.match_off_h, self.nB)]
 
+    def assign(self, stream=None):
+        """Optimal-assignment matching of every pair's S (call after run() of a
+        batch built with want_S=True): (matches, scores), device tensors laid
+        out like the greedy ones (match_off) and one FP64 score per pair."""
+        if self.S is None:
+            raise ValueError("the assignment reads S: build the Batch with want_S=True")
+        dev = self.S.device
+        off = np.concatenate([[0], np.cumsum(self.nB)]).astype(np.int64)
+        match = torch.empty(max(int(off[-1]), 1), dtype=torch.int32, device=dev)
+        match_off = torch.as_tensor(off[:-1]).to(dev)
+        scores = torch.empty(max(self.n_pairs, 1), dtype=torch.float64, device=dev)
+        nr = torch.as_tensor(self.nB.astype(np.int32)).to(dev)
+        nc = torch.as_tensor(self.nA.astype(np.int32)).to(dev)
+        max_dim = int(max(int(self.nA.max(initial=1)), int(self.nB.max(initial=1)), 1))
+        _check(lib().cfsim_assign(self.ctx.handle, self.opt.dtype, _ptr(self.S), _ptr(self.S_off), _ptr(nr),
+                                  _ptr(nc), self.n_pairs, max_dim, _ptr(match), _ptr(match_off), _ptr(scores),
+                                  _stream(stream)))
+        self._assign_keep = (nr, nc, match_off)  # alive until the stream has used them
+        return match, scores[: self.n_pairs]
+
     def S_list(self):
         S = self.S.cpu().numpy()
         return [S[o:o + a * b].reshape(b, a) for o, a, b in zip(self.S_off_h, self.nA, self.nB)]
@@ -583,3 +604,26 @@ def score_damped(ctx, gs, pair_a, pair_b, alpha=0.85, prior=None, dtype="f32", m
     b.run()
     torch.cuda.synchronize()
     return b.results(), (b.matches() if want_match else None), (b.S_list() if want_S else None)
+
+
+def assign(ctx, S_list, dtype="f64", stream=None):
+    """Optimal-assignment matching (cfsim_assign) of host matrices: returns
+    (list of row -> column arrays, scores)."""
+    mats = [np.asarray(x) for x in S_list]
+    npdt = np.float64 if dtype == "f64" else np.float32
+    flat = np.concatenate([m.astype(npdt).ravel() for m in mats]) if mats else np.zeros(1, npdt)
+    off = np.concatenate([[0], np.cumsum([m.size for m in mats])]).astype(np.int64)
+    nr = np.array([m.shape[0] for m in mats], np.int32)
+    nc = np.array([m.shape[1] for m in mats], np.int32)
+    moff = np.concatenate([[0], np.cumsum(nr)]).astype(np.int64)
+    dev = torch.device("cuda", ctx.device)
+    t = lambda a: torch.as_tensor(a).to(dev)
+    dS, dSo, dnr, dnc, dmo = t(flat), t(off[:-1]), t(nr), t(nc), t(moff[:-1])
+    match = torch.empty(max(int(moff[-1]), 1), dtype=torch.int32, device=dev)
+    scores = torch.empty(max(len(mats), 1), dtype=torch.float64, device=dev)
+    max_dim = int(max([max(m.shape) for m in mats], default=1))
+    _check(lib().cfsim_assign(ctx.handle, F64 if dtype == "f64" else F32, _ptr(dS), _ptr(dSo), _ptr(dnr), _ptr(dnc),
+                              len(mats), max_dim, _ptr(match), _ptr(dmo), _ptr(scores), _stream(stream)))
+    torch.cuda.synchronize()
+    m = match.cpu().numpy()
+    return [m[o:o + r] for o, r in zip(moff[:-1], nr)], scores[: len(mats)].cpu().numpy()

@@ -1124,3 +1124,29 @@ cfsim_status cfsim_distances(cfsim_context* ctx, const cfsim_graph_set* set, con
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ optimal-assignment matching
+cfsim_status cfsim_assign(cfsim_context* ctx, int32_t dtype, const void* S, const int64_t* S_off,
+                          const int32_t* n_rows, const int32_t* n_cols, int64_t n_pairs, int32_t max_dim,
+                          int32_t* match, const int64_t* match_off, double* score, void* stream) {
+    if (dtype != CFSIM_F64 && dtype != CFSIM_F32) return fail(CFSIM_E_INVALID_ARG, "dtype must be CFSIM_F64 or CFSIM_F32");
+    if (n_pairs < 0) return fail(CFSIM_E_INVALID_ARG, "n_pairs must be >= 0");
+    if (n_pairs > INT32_MAX) return fail(CFSIM_E_UNSUPPORTED, "more than 2^31-1 matrices in one call");
+    if (max_dim < 1) return fail(CFSIM_E_INVALID_ARG, "max_dim must be >= 1");
+    if (max_dim > cfsim::kAssignMaxDim)
+        return fail(CFSIM_E_UNSUPPORTED, "max_dim above %d (the LDS state of one matrix)", cfsim::kAssignMaxDim);
+    if (n_pairs > 0 && (!S || !S_off || !n_rows || !n_cols || !score))
+        return fail(CFSIM_E_INVALID_ARG, "S, S_off, n_rows, n_cols or score is NULL");
+    if ((match == nullptr) != (match_off == nullptr))
+        return fail(CFSIM_E_INVALID_ARG, "match and match_off must both be given or both be NULL");
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_pairs == 0) return ok();
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    const int64_t cap = (int64_t)num_cus_of(ctx) * 32;
+    const int grid = (int)(n_pairs < cap ? n_pairs : cap);
+    e = cfsim::launch_assign(dtype, S, S_off, n_rows, n_cols, (int)n_pairs, max_dim, match, match_off, score, grid,
+                             static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "assignment launch");
+    return ok();
+}

@@ -379,4 +379,12 @@ int dist_grid(int num_cus);
 int launch_distances(const SetRef& set, int max_nodes, const int32_t* pa, const int32_t* pb, int n_pairs, double p,
                      double* out, int64_t* task_off, double* part, int grid, hipStream_t stream);
 
+// Optimal-assignment matching (assign.hip): LDS bytes of one workgroup for
+// matrices of at most max_dim rows and columns.
+constexpr int kAssignMaxDim = 4096;
+size_t assign_lds_bytes(int max_dim);
+int launch_assign(int dtype, const void* S, const int64_t* S_off, const int32_t* n_rows, const int32_t* n_cols,
+                  int n_pairs, int max_dim, int32_t* match, const int64_t* match_off, double* score, int grid,
+                  hipStream_t stream);
+
 }  // namespace cfsim

@@ -444,3 +444,26 @@ def test_damped_arguments_checked_on_the_host(alpha, prior, prior_off, opt_kw, c
                                0x1000, None, None, None, None, 0x1000, 1 << 40, None)
     assert got == code
     assert text in L.cfsim_last_error().decode()
+
+
+@pytest.mark.parametrize("dtype,n_pairs,max_dim,ptrs,code,text", [
+    (5, 3, 16, {}, -1, "dtype"),
+    (0, -1, 16, {}, -1, "n_pairs"),
+    (0, 3, 0, {}, -1, "max_dim"),
+    (1, 3, 5000, {}, -6, "max_dim"),
+    (0, 3, 16, dict(S=None), -1, "NULL"),
+    (0, 3, 16, dict(score=None), -1, "NULL"),
+    (0, 3, 16, dict(match_off=None), -1, "match"),
+    (0, 3, 16, {}, -1, "context"),
+])
+def test_assign_arguments_checked_on_the_host(dtype, n_pairs, max_dim, ptrs, code, text):
+    L = cf.lib()
+    P = 0x1000
+    a = dict(S=P, S_off=P, n_rows=P, n_cols=P, match=P, match_off=P, score=P)
+    a.update(ptrs)
+    got = L.cfsim_assign(None, dtype, a["S"], a["S_off"], a["n_rows"], a["n_cols"], n_pairs, max_dim, a["match"],
+                         a["match_off"], a["score"], None)
+    assert got == code
+    assert text in L.cfsim_last_error().decode()
+    # no matrix: nothing to do and no HIP call
+    assert L.cfsim_assign(P, 0, None, None, None, None, 0, 16, None, None, None, None) == 0
