@@ -273,8 +273,8 @@ def workload_legs(ctx, stream, reps=3):
     """The other hot-path rows, each on its own synthetic workload: the plain
     12 x 16 pair, large pairs (tiled path), query-vs-database with top-16,
     the reverse mode, the scale-to-common-size mode of the all-pairs batch,
-    the elementwise distances of Table 1, the damped IsoRank measure and the
-    optimal-assignment matching.  Inputs resident in HBM; every time is the average of `reps` timed
+    the elementwise distances of Table 1, the damped IsoRank measure, the
+    optimal-assignment matching and Ward's clustering.  Inputs resident in HBM; every time is the average of `reps` timed
     calls after one warm-up; every leg states its error against the FP64 GPU
     path (itself parity-tested against the CPU oracle)."""
     import torch
@@ -499,6 +499,35 @@ def workload_legs(ctx, stream, reps=3):
                              ms_per_call=ms, pairs_per_s=len(sc) / (ms * 1e-3), all_finite=bool(np.isfinite(sc).all()),
                              pairs_above_greedy=int(np.sum(gain > 1e-6)), max_gain_over_greedy=float(gain.max()),
                              mean_gain_over_greedy=float(gain.mean()), min_gain_over_greedy=float(gain.min()))
+    del b, gs
+
+    # f4: Ward's clustering (squared Euclidean distances, Lance-Williams
+    # merges) of the 256 graphs, each described by its row of the all-pairs
+    # FP32 score matrix (self pairs on the diagonal); and of 4,096 seeded
+    # points with 16 features (the largest size one workgroup's merge state
+    # holds)
+    w = config_graphs(1)
+    G = len(w["graphs"])
+    gs = cf.pack(ctx, w["graphs"])
+    ia, ib = np.triu_indices(G)
+    b = cf.Batch(ctx, gs, ia.astype(np.int32), ib.astype(np.int32), dtype="f32", want_match=False)
+    b.run()
+    torch.cuda.synchronize()
+    sc = b.results()["score"]
+    M = np.zeros((G, G))
+    M[ia, ib] = sc
+    M[ib, ia] = sc
+    Md = torch.as_tensor(M).to(gs.w.device)
+    cf.ward(ctx, Md, stream=stream)
+    torch.cuda.synchronize()
+    ms = _time_ms(lambda: cf.ward(ctx, Md, stream=stream), reps, stream)
+    Xr = torch.as_tensor(np.random.default_rng(170702423).random((4096, 16))).to(gs.w.device)
+    cf.ward(ctx, Xr, stream=stream)
+    torch.cuda.synchronize()
+    ms_big = _time_ms(lambda: cf.ward(ctx, Xr, stream=stream), 1, stream)
+    out["ward"] = dict(workload="Ward clustering of the 256 graphs by their rows of the all-pairs FP32 score matrix "
+                                "(256 features); and of 4,096 seeded points with 16 features",
+                       ms_per_call=ms, merges_per_s=(G - 1) / (ms * 1e-3), ms_4096_points=ms_big)
     del b, gs
     return out
 

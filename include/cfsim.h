@@ -495,6 +495,32 @@ cfsim_status cfsim_assign(cfsim_context* ctx, int32_t dtype, const void* S, cons
                           const int32_t* n_rows, const int32_t* n_cols, int64_t n_pairs, int32_t max_dim,
                           int32_t* match, const int64_t* match_off, double* score, void* stream);
 
+/*
+ * Ward's minimum-variance clustering (Section 6.2, Clustering of Kernels):
+ * X is n_obs x n_feat row-major FP64 (device), one feature vector per
+ * observation (e.g. each graph's row of an all-pairs score or distance
+ * matrix).  Initial distances are squared Euclidean, d_ij = ||X_i - X_j||^2
+ * (features added in order); each of the n_obs - 1 merges joins the pair of
+ * current clusters with the smallest distance (ties: the pair of smaller
+ * slots, slot i < j, the merged cluster taking slot i), and distances to
+ * the merged cluster follow the Lance-Williams recurrence of Ward's method:
+ *   d(k, i u j) = ((n_i + n_k) d_ki + (n_j + n_k) d_kj - n_k d_ij)
+ *                 / (n_i + n_j + n_k),
+ * so a merge height is twice the increase in within-cluster variance
+ * (scipy's Ward heights are its square root).  Z (device, (n_obs - 1) x 4
+ * FP64, row-major) receives the usual linkage layout: row s =
+ * [id_a, id_b, height, size], id_a < id_b, observations numbered
+ * 0..n_obs-1 and the cluster of step s numbered n_obs + s.  A non-finite
+ * feature makes every entry of Z NaN.  FP64 arithmetic without fused
+ * multiply-adds, in the order above: the result is reproducible bit for bit.
+ * ws: device workspace of cfsim_ward_workspace_size(n_obs) bytes (the
+ * n_obs x n_obs distances).  1 <= n_obs <= 4096 (more: CFSIM_E_UNSUPPORTED),
+ * n_feat >= 1; n_obs = 1 writes nothing.
+ */
+size_t cfsim_ward_workspace_size(int32_t n_obs);
+cfsim_status cfsim_ward(cfsim_context* ctx, const double* X, int32_t n_obs, int32_t n_feat, double* Z, void* ws,
+                        size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/api.hip", "csrc/pack.hip", "csrc/pair.hip", "csrc/topk.hip", "csrc/adjoint.hip", "csrc/large.hip",
-           "csrc/large_mfma.hip", "csrc/distances.hip", "csrc/assign.hip"]
+           "csrc/large_mfma.hip", "csrc/distances.hip", "csrc/assign.hip",
+           "csrc/ward.hip"]
 LIB = os.path.join(HERE, "libcfsim.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

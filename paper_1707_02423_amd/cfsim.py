@@ -106,6 +106,8 @@ SIGNATURES = {
     "cfsim_score_damped": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.POINTER(Options),
                                           ctypes.c_double, _P, _P, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     "cfsim_assign": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _I64, _I32, _P, _P, _P, _P]),
+    "cfsim_ward_workspace_size": (_SZ, [_I32]),
+    "cfsim_ward": (ctypes.c_int, [_P, _P, _I32, _I32, _P, _P, _SZ, _P]),
     "cfsim_distances_workspace_size": (_SZ, [ctypes.POINTER(GraphSetC), _I64]),
     "cfsim_distances": (ctypes.c_int, [_P, ctypes.POINTER(GraphSetC), _P, _P, _I64, ctypes.c_double, _P, _P, _SZ,
                                        _P]),
@@ -627,3 +629,17 @@ def assign(ctx, S_list, dtype="f64", stream=None):
     torch.cuda.synchronize()
     m = match.cpu().numpy()
     return [m[o:o + r] for o, r in zip(moff[:-1], nr)], scores[: len(mats)].cpu().numpy()
+
+
+def ward(ctx, X, stream=None) -> torch.Tensor:
+    """Ward's clustering of the rows of X (cfsim_ward): the (n - 1) x 4 FP64
+    linkage matrix on the device.  X: host array or FP64 device tensor."""
+    dev = torch.device("cuda", ctx.device)
+    Xd = X.to(device=dev, dtype=torch.float64).contiguous() if isinstance(X, torch.Tensor) else \
+        torch.as_tensor(np.ascontiguousarray(X, np.float64)).to(dev)
+    n, f = int(Xd.shape[0]), int(Xd.shape[1])
+    Z = torch.empty((max(n - 1, 1), 4), dtype=torch.float64, device=dev)
+    ws_bytes = lib().cfsim_ward_workspace_size(n)
+    ws = torch.empty(max(ws_bytes, 1), dtype=torch.uint8, device=dev)
+    _check(lib().cfsim_ward(ctx.handle, _ptr(Xd), n, f, _ptr(Z), _ptr(ws), ws_bytes, _stream(stream)))
+    return Z[: max(n - 1, 0)]

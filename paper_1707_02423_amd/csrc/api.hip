@@ -1150,3 +1150,28 @@ cfsim_status cfsim_assign(cfsim_context* ctx, int32_t dtype, const void* S, cons
     if (e != 0) return hip_fail(e, "assignment launch");
     return ok();
 }
+
+// ------------------------------------------------------------------ Ward's clustering (Section 6.2)
+size_t cfsim_ward_workspace_size(int32_t n_obs) {
+    if (n_obs < 1 || n_obs > cfsim::kWardMaxObs) return 0;
+    return align256((size_t)n_obs * (size_t)n_obs * sizeof(double));
+}
+
+cfsim_status cfsim_ward(cfsim_context* ctx, const double* X, int32_t n_obs, int32_t n_feat, double* Z, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (n_obs < 1) return fail(CFSIM_E_INVALID_ARG, "n_obs must be >= 1");
+    if (n_feat < 1) return fail(CFSIM_E_INVALID_ARG, "n_feat must be >= 1");
+    if (n_obs > cfsim::kWardMaxObs)
+        return fail(CFSIM_E_UNSUPPORTED, "more than %d observations (the merge state of one workgroup)",
+                    cfsim::kWardMaxObs);
+    if (!X || (n_obs > 1 && !Z)) return fail(CFSIM_E_INVALID_ARG, "X or Z is NULL");
+    const size_t need = cfsim_ward_workspace_size(n_obs);
+    if (!ws || ws_bytes < need) return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+    if (n_obs == 1) return ok();
+    int e = (int)hipSetDevice(ctx->device);
+    if (e != 0) return hip_fail(e, "hipSetDevice");
+    e = cfsim::launch_ward(X, n_obs, n_feat, Z, static_cast<double*>(ws), static_cast<hipStream_t>(stream));
+    if (e != 0) return hip_fail(e, "Ward launch");
+    return ok();
+}

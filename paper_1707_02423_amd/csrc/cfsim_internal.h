@@ -387,4 +387,8 @@ int launch_assign(int dtype, const void* S, const int64_t* S_off, const int32_t*
                   int n_pairs, int max_dim, int32_t* match, const int64_t* match_off, double* score, int grid,
                   hipStream_t stream);
 
+// Ward's clustering (ward.hip): distances into D (n x n FP64), then the merges.
+constexpr int kWardMaxObs = 4096;
+int launch_ward(const double* X, int n, int f, double* Z, double* D, hipStream_t stream);
+
 }  // namespace cfsim

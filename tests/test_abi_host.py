@@ -467,3 +467,24 @@ def test_assign_arguments_checked_on_the_host(dtype, n_pairs, max_dim, ptrs, cod
     assert text in L.cfsim_last_error().decode()
     # no matrix: nothing to do and no HIP call
     assert L.cfsim_assign(P, 0, None, None, None, None, 0, 16, None, None, None, None) == 0
+
+
+def test_ward_arguments_checked_on_the_host():
+    L = cf.lib()
+    P = 0x1000
+    assert L.cfsim_ward_workspace_size(100) >= 100 * 100 * 8
+    assert L.cfsim_ward_workspace_size(0) == 0 and L.cfsim_ward_workspace_size(5000) == 0
+    cases = [
+        ((P, P, 0, 3, P, P, 1 << 20, None), -1, "n_obs"),
+        ((P, P, 10, 0, P, P, 1 << 20, None), -1, "n_feat"),
+        ((P, P, 5000, 3, P, P, 1 << 40, None), -6, "observations"),
+        ((P, None, 10, 3, P, P, 1 << 20, None), -1, "NULL"),
+        ((P, P, 10, 3, None, P, 1 << 20, None), -1, "NULL"),
+        ((P, P, 10, 3, P, P, 16, None), -5, "workspace"),
+        ((None, P, 10, 3, P, P, 1 << 20, None), -1, "context"),
+    ]
+    for args, code, text in cases:
+        assert L.cfsim_ward(*args) == code, args
+        assert text in L.cfsim_last_error().decode()
+    # one observation: no merge, no HIP call
+    assert L.cfsim_ward(P, P, 1, 3, None, P, 1 << 20, None) == 0
