@@ -862,12 +862,23 @@ __device__ __forceinline__ void greedy_walk_lds(const PairShape& sh, const T* S,
 }
 
 // Kept out of line: runs once per pair, and inlined it constrains the
-// register allocation of the update loop in the same kernel.
+// register allocation of the update loop in the same kernel.  Its arguments
+// are scalars: a shape or list record passed by reference would have to live
+// in the caller's stack, written once per pair by every thread.
 template <typename T, int NT>
-__device__ __noinline__ void greedy_sorted(const PairShape& sh, const T* S, T* St, const Lists<T>& G) {
+__device__ __noinline__ void greedy_sorted(int nR, int nC, int swp, const T* S, T* St, int* rstate, int* rbest,
+                                           int* cstate, void* rec) {
     constexpr int NW = NT / kWave;
     const int wave = uni((int)threadIdx.x / kWave);
-    const int nR = sh.nR, nC = sh.nC;
+    PairShape sh{};
+    sh.swap = swp;
+    sh.nR = nR;
+    sh.nC = nC;
+    Lists<T> G{};
+    G.rstate = rstate;
+    G.rbest = rbest;
+    G.cstate = cstate;
+    G.rec = reinterpret_cast<RowRec<T>*>(rec);
     uint16_t* ord = reinterpret_cast<uint16_t*>(St);
     // rows sorted together by a wave: 4 short ones, 2 of 65-128 entries, 1 longer
     if (nC <= kWave) {
@@ -1051,7 +1062,7 @@ __device__ __forceinline__ void match_and_write(const PairJob& J, int p, const G
     int* rstate = G.rstate;
     int* cstate = G.cstate;
     if (nC <= kSortCols)
-        greedy_sorted<T, NT>(sh, S, St, G);
+        greedy_sorted<T, NT>(sh.nR, nC, sh.swap, S, St, G.rstate, G.rbest, G.cstate, G.rec);
     else
         greedy_rounds<T, NT>(sh, S, St, G, s_count);
     // the row records and column infos are free now: they hold the picks
