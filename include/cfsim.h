@@ -251,9 +251,12 @@ cfsim_status cfsim_score_noalloc(cfsim_context* ctx, const cfsim_graph* A, const
  * Device buffers: pair_a/pair_b[n_pairs], res[n_pairs]; optional (NULL to
  * skip): match with match_off[n_pairs] (element offset of pair p's n_B
  * entries), S_out with S_off[n_pairs] (element offset of pair p's S).
- * Resized calls (opt->resize = CFSIM_RESIZE_BILINEAR) run every pair on the
- * tiled path of cfsim_score_large; S and match of pair p then have n_M x n_M
- * and n_M entries, n_M = max(n_A, n_B).
+ * Resized calls (opt->resize = CFSIM_RESIZE_BILINEAR): S and match of pair p
+ * have n_M x n_M and n_M entries, n_M = max(n_A, n_B).  The LDS kernels run
+ * every pair they hold in a resized mode (the operator in factored form at
+ * n_M x min(n_A, n_B), with the larger graph on the rows, expanded to
+ * n_M x n_M for the matching); the others run on the tiled path of
+ * cfsim_score_large in the same call.
  */
 size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_set* set,
                                   int64_t n_pairs, const cfsim_options* opt);
@@ -292,7 +295,8 @@ cfsim_status cfsim_score_large(cfsim_context* ctx, const cfsim_graph_set* set,
  * Batch schedule and kernel timing (observability of the batched path).
  * Every pair of a batch runs in one of CFSIM_NUM_BUCKETS buckets: 0..4 are
  * the LDS-resident pair kernels in increasing size, 5 the global-memory pair
- * kernel, 6 the pairs no kernel takes (they get CFSIM_INVALID_INPUT).
+ * kernel, 6 the pairs no kernel takes (they get CFSIM_INVALID_INPUT; in a
+ * resized call, the pairs left to the tiled path).
  *   cfsim_batch_buckets: writes the bucket cfsim_score_batch would give each
  *     pair to bucket[n_pairs] (device int32), on `stream`.  Same argument
  *     rules as cfsim_score_batch; no workspace.

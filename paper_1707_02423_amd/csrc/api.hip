@@ -219,6 +219,21 @@ size_t batch_ws_bytes(const cfsim_context* ctx, int64_t n_pairs, int esize, int 
     for (int v = 0; v <= cfsim::kBucketGlobal; ++v) b += slot_bytes(ctx, v, esize, max_nodes);
     return b;
 }
+// The schedule part of the batch workspace alone (order, bounds, queues).
+size_t sched_ws_bytes(int64_t n_pairs) {
+    return align256((size_t)n_pairs * 4) + align256(2 * cfsim::kBuckets * 4) + align256(cfsim::kBuckets * 4);
+}
+BatchWs carve_sched(void* ws, int64_t n_pairs) {
+    unsigned char* p = static_cast<unsigned char*>(ws);
+    BatchWs b;
+    b.order = reinterpret_cast<int32_t*>(p);
+    p += align256((size_t)n_pairs * 4);
+    b.bounds = reinterpret_cast<int32_t*>(p);
+    p += align256(2 * cfsim::kBuckets * 4);
+    b.queues = reinterpret_cast<int32_t*>(p);
+    for (int v = 0; v <= cfsim::kBucketGlobal; ++v) b.slots[v] = nullptr;
+    return b;
+}
 BatchWs carve_batch(const cfsim_context* ctx, void* ws, int64_t n_pairs, int esize, int max_nodes) {
     unsigned char* p = static_cast<unsigned char*>(ws);
     BatchWs b;
@@ -666,7 +681,9 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
     if (n_pairs < 0 || !set || !opt || set->max_nodes < 1) return 0;
     if (opt->resize == CFSIM_RESIZE_BILINEAR) {
         if (set->max_nodes > cfsim::kLargeMaxNodes) return 0;
-        return large_ws_bytes(n_pairs > 0 ? n_pairs : 1, set->max_nodes, esize_of(opt->dtype), 6);
+        // the tiled path's workspace, then the LDS kernels' schedule
+        return large_ws_bytes(n_pairs > 0 ? n_pairs : 1, set->max_nodes, esize_of(opt->dtype), 6) +
+               sched_ws_bytes(n_pairs);
     }
     return batch_ws_bytes(ctx, n_pairs, fp64_final(opt) ? 8 : esize_of(opt->dtype), set->max_nodes);
 }
@@ -693,7 +710,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
                         int64_t n_pairs, const cfsim_options* opt, int dtype, const cfsim_pair_result* filter,
                         cfsim_pair_result* res, int32_t* match, const int64_t* match_off, void* S_out,
                         const int64_t* S_off, const BatchWs& b, hipStream_t st, bool timed, const CkptOut& ck,
-                        const Damping& dm) {
+                        const Damping& dm, int resize = 0) {
     const int esize = esize_of(dtype);
     cfsim::PlanJob plan{};
     plan.set = ref_of(set);
@@ -707,6 +724,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     plan.bounds = b.bounds;
     plan.queues = b.queues;
     memcpy(plan.tune, ctx->tune[dtype_index(dtype)], sizeof(plan.tune));
+    plan.resize = resize;
     int e = cfsim::launch_plan(plan, st);
     if (e != 0) return e;
     cfsim::PairJob job{};
@@ -727,6 +745,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     job.ckpt = ck.ptr;
     job.ckpt_off = ck.off;
     job.ckpt_every = ck.every;
+    job.resize = resize;
     job.damped = dm.on;
     job.alpha = dm.alpha;
     job.prior = dm.prior;
@@ -784,6 +803,26 @@ static int enqueue_large(cfsim_context* ctx, const cfsim_graph_set* set, const i
     return cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)), st);
 }
 
+// Resized batch: the LDS kernels in their resized mode take every pair they
+// hold; the tiled path then runs the pairs they left invalid (pairs too large
+// for LDS, and pairs with bad ids, which it marks invalid itself).
+static int enqueue_resized(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
+                           const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt, cfsim_pair_result* res,
+                           int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
+                           hipStream_t st) {
+    const size_t lb = large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype), 6);
+    const BatchWs b = carve_sched(static_cast<unsigned char*>(ws) + lb, n_pairs);
+    int e = enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, opt->dtype, nullptr, res, match, match_off, S_out,
+                         S_off, b, st, false, CkptOut{nullptr, nullptr, 0}, Damping{0, 0.0, nullptr, nullptr}, 1);
+    if (e != 0) return e;
+    cfsim::LargeJob J = large_job(opt, n_pairs, set->max_nodes, res, match, match_off, S_out, S_off, ws);
+    J.set = ref_of(set);
+    J.pair_a = pair_a;
+    J.pair_b = pair_b;
+    J.filter = res;
+    return cfsim::launch_large(opt->dtype, J, cfsim::large_step_grid(num_cus_of(ctx)), st);
+}
+
 // The tiled path over the pairs of a set (large pairs; every pair when resized).
 static cfsim_status run_large(cfsim_context* ctx, const cfsim_graph_set* set, const int32_t* pair_a,
                               const int32_t* pair_b, int64_t n_pairs, const cfsim_options* opt,
@@ -830,9 +869,18 @@ static cfsim_status score_batch(cfsim_context* ctx, const cfsim_graph_set* set, 
     if (e != 0) return hip_fail(e, "hipSetDevice");
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (resize) {
-        // scaled pairs run on the tiled path (the resized operator in factored form)
+        // the resized operator in factored form: LDS kernels, the rest on the tiled path
         ctx->timed = 0;
-        return run_large(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+        if (ctx->timing || graphs_disabled()) {
+            e = enqueue_resized(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st);
+            if (e != 0) return hip_fail(e, "resized batch launch");
+            return ok();
+        }
+        auto key = set_call_key(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws);
+        return replay_or_capture(ctx, &ctx->graph, &ctx->exec, &ctx->key, key, st, [&](hipStream_t cs) {
+            return enqueue_resized(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws,
+                                   cs);
+        });
     }
     if (ctx->timing || graphs_disabled()) {
         e = enqueue_batch(ctx, set, pair_a, pair_b, n_pairs, opt, res, match, match_off, S_out, S_off, ws, st,
@@ -905,8 +953,6 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     if (n_pairs > 0 && (!pair_a || !pair_b || !bucket))
         return fail(CFSIM_E_INVALID_ARG, "pair_a, pair_b or bucket is NULL");
     if (set->max_nodes > 65536) return fail(CFSIM_E_UNSUPPORTED, "max_nodes above 65536");
-    if (opt->resize == CFSIM_RESIZE_BILINEAR)
-        return fail(CFSIM_E_UNSUPPORTED, "resized pairs run on the tiled path, which has no buckets");
     if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
     if (n_pairs == 0) return ok();
     int e = (int)hipSetDevice(ctx->device);
@@ -919,6 +965,7 @@ cfsim_status cfsim_batch_buckets(cfsim_context* ctx, const cfsim_graph_set* set,
     plan.n_pairs = n_pairs;
     plan.esize = esize_of(opt->dtype);
     plan.slot_elems = global_slot_elems(set->max_nodes);
+    plan.resize = opt->resize == CFSIM_RESIZE_BILINEAR ? 1 : 0;
     e = cfsim::launch_buckets(plan, bucket, static_cast<hipStream_t>(stream));
     if (e != 0) return hip_fail(e, "bucket launch");
     return ok();

@@ -49,6 +49,66 @@ __host__ __device__ inline GraphRef graph_of(const SetRef& s, int g) {
     return r;
 }
 
+// ---------------------------------------------------------------- scale to a common size
+// The order-1 interpolation matrix R (M x m) of Section 4.1 and G = R^T R,
+// used by the tiled path and by the LDS kernels' resized mode.
+// Interpolation from m to M points at p (m - 1) / (M - 1): row p of R holds
+// 1 - f at column r0 and f at column r1 (one entry 1 when r0 = r1).
+struct Interp {
+    int r0, r1;
+    double f;
+};
+__host__ __device__ inline Interp interp_at(int p, int m, int M) {
+    Interp q;
+    if (M <= 1) {
+        q.r0 = q.r1 = 0;
+        q.f = 0.0;
+        return q;
+    }
+    const long long num = (long long)p * (m - 1);
+    q.r0 = (int)(num / (M - 1));
+    q.f = (double)(num - (long long)q.r0 * (M - 1)) / (double)(M - 1);
+    q.r1 = q.r0 + 1 < m ? q.r0 + 1 : m - 1;
+    return q;
+}
+
+// First and last p with r0(p) = u.
+__host__ __device__ inline void interp_rows(int u, int m, int M, int* plo, int* phi) {
+    if (m <= 1) {
+        *plo = 0;
+        *phi = M - 1;
+        return;
+    }
+    const long long a = (long long)u * (M - 1), b = (long long)(u + 1) * (M - 1);
+    *plo = (int)((a + (m - 2)) / (m - 1));
+    *phi = u == m - 1 ? M - 1 : (int)((b + (m - 2)) / (m - 1)) - 1;
+}
+
+// G = R^T R at column u: diagonal d and the coupling e = G[u][u+1].
+__host__ __device__ inline void gram_entries(int u, int m, int M, double* d, double* e) {
+    double dd = 0.0, ee = 0.0;
+    int lo, hi;
+    interp_rows(u, m, M, &lo, &hi);
+    for (int p = lo; p <= hi; ++p) {
+        const Interp q = interp_at(p, m, M);
+        if (q.r1 == q.r0) {
+            dd += 1.0;  // (1 - f + f)^2 with a single entry
+        } else {
+            dd += (1.0 - q.f) * (1.0 - q.f);
+            ee += (1.0 - q.f) * q.f;
+        }
+    }
+    if (u > 0) {
+        interp_rows(u - 1, m, M, &lo, &hi);
+        for (int p = lo; p <= hi; ++p) {
+            const Interp q = interp_at(p, m, M);
+            if (q.r1 == u && q.r0 != q.r1) dd += q.f * q.f;
+        }
+    }
+    *d = dd;
+    *e = ee;
+}
+
 // ---------------------------------------------------------------- pair shape
 // The kernels store S in a "compute orientation": rows are the nodes of the
 // R graph (handled wave-uniformly), columns the nodes of the C graph (one lane
@@ -157,6 +217,24 @@ __host__ __device__ inline bool choose_shape(int nA, int nB, int nnzA, int nnzB,
     return false;
 }
 
+// Resized mode of the LDS kernels (pairs of unequal sizes, M = the larger
+// node count, m = the smaller): the iteration keeps U_even, V_a, V_b (M x m
+// each) and the lists of the larger graph's rows and the smaller graph's
+// columns; the matching then needs S and S^T at M x M and a fresh set of
+// matching arrays.  The larger graph always takes the rows.
+__host__ __device__ inline size_t resized_iter_bytes(int M, int m, int nnzR, int nnzC, int esize) {
+    return 3 * align16((size_t)M * m * esize) + lds_lists_bytes(M, m, nnzR, nnzC, esize);
+}
+__host__ __device__ inline size_t resized_match_bytes(int M, int esize) {
+    return 2 * align16((size_t)M * M * esize) + lds_lists_bytes(M, M, 0, 0, esize);
+}
+__host__ __device__ inline bool resized_fits(int M, int m, int nnzR, int nnzC, int variant, int esize) {
+    const Variant v = variant_info(variant, esize);
+    if ((m + 63) / 64 > v.nch) return false;
+    const size_t it = resized_iter_bytes(M, m, nnzR, nnzC, esize), mt = resized_match_bytes(M, esize);
+    return (it > mt ? it : mt) <= (size_t)v.lds_bytes;
+}
+
 // ---------------------------------------------------------------- launch descriptors
 struct PairJob {
     // pairs: either one explicit pair (single = 1) or pairs of a graph set
@@ -193,6 +271,10 @@ struct PairJob {
     void* ckpt;
     const int64_t* ckpt_off;
     int ckpt_every;
+    // Scale to a common size (resize = 1): pairs of unequal sizes run the
+    // resized operator in factored form (rows: the larger graph, M nodes;
+    // columns: the smaller one, m nodes; see iterate_resized)
+    int resize;
     // Damped measure (damped = 1): the fixed point of x = alpha M_hat x +
     // (1 - alpha) E with M_hat the operator with unit column sums and E the
     // prior (NULL: uniform; else pair p's n_B x n_A FP64 prior at
@@ -237,6 +319,9 @@ struct PlanJob {
     int32_t* queues;
     // LDS variant per tune class (-1: the first variant that holds the pair)
     int8_t tune[kTuneClasses];
+    // resized mode: pairs of unequal sizes are planned on their resized LDS
+    // footprint; pairs no LDS kernel holds are left to the tiled path
+    int resize;
 };
 
 // Host-side launchers (return hipError_t as int).
@@ -285,6 +370,9 @@ struct LargeState {
 };
 
 struct LargeJob {
+    // if set: only pairs whose result here carries CFSIM_INVALID_INPUT run
+    // (the rest were scored by the LDS kernels and keep their results)
+    const cfsim_pair_result* filter;
     int single;          // one explicit pair (ga, gb) instead of pairs of a set
     GraphRef ga, gb;
     SetRef set;

@@ -108,71 +108,27 @@ __device__ inline void state_graphs(const LargeJob& J, int p, const LargeState* 
     *Cg = s->swap ? B : A;
 }
 
-// Interpolation from m to M points at p (m - 1) / (M - 1): row p of R holds
-// 1 - f at column r0 and f at column r1 (one entry 1 when r0 = r1).
-struct Interp {
-    int r0, r1;
-    double f;
-};
-__device__ inline Interp interp_at(int p, int m, int M) {
-    Interp q;
-    if (M <= 1) {
-        q.r0 = q.r1 = 0;
-        q.f = 0.0;
-        return q;
-    }
-    const long long num = (long long)p * (m - 1);
-    q.r0 = (int)(num / (M - 1));
-    q.f = (double)(num - (long long)q.r0 * (M - 1)) / (double)(M - 1);
-    q.r1 = q.r0 + 1 < m ? q.r0 + 1 : m - 1;
-    return q;
-}
-
-// First and last p with r0(p) = u.
-__device__ inline void interp_rows(int u, int m, int M, int* plo, int* phi) {
-    if (m <= 1) {
-        *plo = 0;
-        *phi = M - 1;
-        return;
-    }
-    const long long a = (long long)u * (M - 1), b = (long long)(u + 1) * (M - 1);
-    *plo = (int)((a + (m - 2)) / (m - 1));
-    *phi = u == m - 1 ? M - 1 : (int)((b + (m - 2)) / (m - 1)) - 1;
-}
-
-// G = R^T R at column u: diagonal d and the coupling e = G[u][u+1].
-__device__ inline void gram_entries(int u, int m, int M, double* d, double* e) {
-    double dd = 0.0, ee = 0.0;
-    int lo, hi;
-    interp_rows(u, m, M, &lo, &hi);
-    for (int p = lo; p <= hi; ++p) {
-        const Interp q = interp_at(p, m, M);
-        if (q.r1 == q.r0) {
-            dd += 1.0;  // (1 - f + f)^2 with a single entry
-        } else {
-            dd += (1.0 - q.f) * (1.0 - q.f);
-            ee += (1.0 - q.f) * q.f;
-        }
-    }
-    if (u > 0) {
-        interp_rows(u - 1, m, M, &lo, &hi);
-        for (int p = lo; p <= hi; ++p) {
-            const Interp q = interp_at(p, m, M);
-            if (q.r1 == u && q.r0 != q.r1) dd += q.f * q.f;
-        }
-    }
-    *d = dd;
-    *e = ee;
-}
-
 // ---------------------------------------------------------------- set-up
 // One workgroup per pair: validity, degeneracy, state shape, initial state,
 // and the node records of the row graph's rows and the column graph's columns.
+// Internal state bit of a pair this call leaves alone (scored by the LDS
+// kernels before; see LargeJob::filter): no tiles, no outputs.
+constexpr unsigned kSkipped = 0x80000000u;
+
 template <typename T>
 __global__ __launch_bounds__(256) void large_init(LargeJob J) {
     const int p = blockIdx.x;
     __shared__ int pos[2];
     LargeState* s = J.st + p;
+    if (J.filter && !(J.filter[p].status & CFSIM_INVALID_INPUT)) {
+        if (threadIdx.x == 0) {
+            s->ntiles = 0;
+            s->active = 0;
+            s->rz = 0;
+            s->status = CFSIM_INVALID_INPUT | kSkipped;
+        }
+        return;
+    }
     GraphRef A{}, B{};
     const bool ok_ids = pair_graphs(J, p, &A, &B);
     const int nA = ok_ids ? A.n : 0, nB = ok_ids ? B.n : 0;
@@ -931,7 +887,7 @@ __global__ __launch_bounds__(kFinishThreads) void large_finish(LargeJob J) {
     const LargeState* s = J.st + p;
     cfsim_pair_result* res = J.res + p;
     if (s->status & CFSIM_INVALID_INPUT) {
-        if (tid == 0) dev::write_invalid(res);
+        if (tid == 0 && !(s->status & kSkipped)) dev::write_invalid(res);
         return;
     }
     const int f = s->final_step;

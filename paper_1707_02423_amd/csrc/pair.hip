@@ -422,6 +422,13 @@ __device__ __forceinline__ IterOut iterate_global(const PairJob& J, const PairSh
     return out;
 }
 
+// What a pair kernel computes: the measure of Table 1's "Iso" row as read
+// throughout (the normalised power iteration), its damped form, or the
+// former with the scale to a common size.
+constexpr int kModePlain = 0;
+constexpr int kModeDamped = 1;
+constexpr int kModeResized = 2;
+
 // ---------------------------------------------------------------- damped measure
 // Table 1's "Iso" row in its full form, (I - alpha Q x P) x = (1 - alpha) E,
 // read with IsoRank's normalisation: M_hat = M D^-1, D the column sums of the
@@ -648,6 +655,212 @@ __device__ inline bool damped_prior(const PairJob& J, int p, int nA, int nB, con
     P.E = E;
     P.scale = 1.0 / sum;
     return true;
+}
+
+// ---------------------------------------------------------------- resized mode
+// Scale to a common size (Section 4 and Section 4.1) for a pair of unequal
+// sizes: the smaller graph X (m nodes) becomes X' = R X R^T with the M x m
+// interpolation R, M the larger node count.  With the larger graph L on the
+// rows,
+//   Y = L S X'^T + L^T S X' = [L (S R) X^T + L^T (S R) X] R^T,
+// so the iteration carries M x m matrices only:
+//   U_k = M_{L,X}(V_{k-1}) / nu_{k-1},   V_k = U_k G   (G = R^T R, tridiagonal),
+//   nu_k^2 = <U_k, U_k G> = ||Y_k||_F^2,  S_k = U_k R^T / nu_k,
+// from U_0 = 1/M (S_0 = 1/M: every row of R sums to 1).  One pass per update
+// forms each row of U_k with the plain gathers over V_{k-1}, then that row of
+// V_k from U_k's neighbouring columns (lane shuffles; a row's chunks are all
+// in one wave) into the other V buffer.  With D = U_k/nu_k - U_{k-2}/nu_{k-2}
+// = a dU + b U_k (dU = U_k - U_{k-2}, a = 1/nu_{k-2}, b = 1/nu_k - a),
+//   delta^2 = <D, D G> = a^2 <dU, dU G> + 2ab <dU, U_k G> + b^2 nu_k^2,
+// three FP64 sums of the same pass (the even-step sums of the plain kernel
+// with G applied).  U is kept only at even updates and at the last one, over
+// U_{k-2}.  The final S (M x M) is expanded in place for the matching.
+
+// Value of column j - 1 (UP) or j + 1 of the same row: lane shuffles inside a
+// chunk, the neighbouring chunk's edge lane across chunks, 0 past the ends.
+template <bool LEFT, typename T, int NCH>
+__device__ __forceinline__ T neighbour(const T (&x)[NCH], int ch) {
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    if constexpr (LEFT) {
+        T v = __shfl_up(x[ch], 1, kWave);
+        if (lane == 0) v = ch > 0 ? lane_value(x[ch > 0 ? ch - 1 : 0], kWave - 1) : T(0);
+        return v;
+    } else {
+        T v = __shfl_down(x[ch], 1, kWave);
+        if (lane == kWave - 1) v = ch + 1 < NCH ? lane_value(x[ch + 1 < NCH ? ch + 1 : 0], 0) : T(0);
+        return v;
+    }
+}
+
+// One update of the resized iteration over the wave's rows: U = sigma M(Vc)
+// (written to Ue when STORE), V = U G into Vn, and the sums.
+template <bool EVEN, bool STORE, typename T, int NT, int NCH>
+__device__ __forceinline__ void resized_rows(const unsigned char* Vc, unsigned char* Vn, unsigned char* Ue, int rowb,
+                                             int nR, const Lists<T>& G, const LaneList<T> (&L)[NCH],
+                                             const uint64_t (&ovf)[NCH], bool any_ovf, const int (&col)[NCH],
+                                             const bool (&cv)[NCH], const T (&gd)[NCH], const T (&ge)[NCH],
+                                             const T (&gm)[NCH], T sigma, EvenSums& es) {
+    constexpr int NW = NT / kWave;
+    const int wave = uni((int)threadIdx.x / kWave);
+    for (int i = wave; i < nR; i += NW) {
+        const RowRec<T> rr = G.rec[i];
+        T y[NCH], u[NCH], du[NCH];
+        update_row<T, NCH>(Vc, rowb, i, rr, G, L, ovf, any_ovf, col, cv, y);
+        T* ue = reinterpret_cast<T*>(Ue + (long long)i * rowb);
+        T* vn = reinterpret_cast<T*>(Vn + (long long)i * rowb);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            u[ch] = cv[ch] ? y[ch] * sigma : T(0);
+            du[ch] = T(0);
+            if constexpr (STORE) {
+                if (cv[ch]) {
+                    if constexpr (EVEN) du[ch] = u[ch] - ue[col[ch]];
+                    ue[col[ch]] = u[ch];
+                }
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const T vg = gm[ch] * neighbour<true, T, NCH>(u, ch) + gd[ch] * u[ch] + ge[ch] * neighbour<false, T, NCH>(u, ch);
+            if (cv[ch]) vn[col[ch]] = vg;
+            es.nu2 += (double)u[ch] * (double)vg;
+            if constexpr (EVEN) {
+                const T dg =
+                    gm[ch] * neighbour<true, T, NCH>(du, ch) + gd[ch] * du[ch] + ge[ch] * neighbour<false, T, NCH>(du, ch);
+                es.dy2 += (double)du[ch] * (double)dg;
+                es.dyy += (double)du[ch] * (double)vg;
+            }
+        }
+    }
+}
+
+// The resized iteration of one pair (M = nR rows of the larger graph, m = nC
+// columns of the smaller); buffers Ue | Va | Vb of B1 bytes each from smem.
+// Returns the outcome; S_final = Ue R^T * out.nu^-1 (Ue = 1/M, nu = 1 if degenerate).
+template <typename T, int NT, int NCH>
+__device__ __forceinline__ IterOut iterate_resized(const PairJob& J, unsigned char* smem, size_t B1,
+                                                   const PairShape& sh, const Lists<T>& G, bool degenerate,
+                                                   double* red) {
+    constexpr int NW = NT / kWave;
+    const int wave = uni((int)threadIdx.x / kWave);
+    const int M = sh.nR, m = sh.nC;
+    const int rowb = m * (int)sizeof(T);
+    unsigned char* Ue = smem;
+    unsigned char* Vc = smem + B1;
+    unsigned char* Vn = smem + 2 * B1;
+    LaneList<T> L[NCH];
+    int col[NCH];
+    bool cv[NCH];
+    uint64_t ovf[NCH];
+    bool any_ovf = false;
+    T gd[NCH], ge[NCH], gm[NCH];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+        lane_setup(G, ch, m, L[ch], col[ch], cv[ch], ovf[ch]);
+        any_ovf |= ovf[ch] != 0;
+        double d = 0.0, e = 0.0, el = 0.0, dl = 0.0;
+        if (cv[ch]) {
+            gram_entries(col[ch], m, M, &d, &e);
+            if (col[ch] > 0) gram_entries(col[ch] - 1, m, M, &dl, &el);
+        }
+        gd[ch] = T(d);
+        ge[ch] = T(e);
+        gm[ch] = T(el);
+    }
+    const T u0 = T(1.0 / (double)M);
+    for (int i = wave; i < M; i += NW) {
+        T* ue = reinterpret_cast<T*>(Ue + (long long)i * rowb);
+        T* vc = reinterpret_cast<T*>(Vc + (long long)i * rowb);
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+            if (cv[ch]) {
+                ue[col[ch]] = u0;
+                vc[col[ch]] = u0 * (gm[ch] + gd[ch] + ge[ch]);
+            }
+    }
+    __syncthreads();
+    IterOut out{0.0, __builtin_inf(), 0, 0u, 0};
+    if (degenerate) {
+        out.status = CFSIM_DEGENERATE;
+        return out;
+    }
+    T sigma = T(1);
+    double a_even = 1.0;  // 1/nu of the last even iterate (U_0 belongs to nu_0 = 1)
+    for (int k = 1; k <= J.max_iter; ++k) {
+        const bool even = (k & 1) == 0, last = k == J.max_iter;
+        EvenSums es{0.0, 0.0, 0.0};
+        if (even)
+            resized_rows<true, true, T, NT, NCH>(Vc, Vn, Ue, rowb, M, G, L, ovf, any_ovf, col, cv, gd, ge, gm, sigma,
+                                                 es);
+        else if (last)
+            resized_rows<false, true, T, NT, NCH>(Vc, Vn, Ue, rowb, M, G, L, ovf, any_ovf, col, cv, gd, ge, gm,
+                                                  sigma, es);
+        else
+            resized_rows<false, false, T, NT, NCH>(Vc, Vn, Ue, rowb, M, G, L, ovf, any_ovf, col, cv, gd, ge, gm,
+                                                   sigma, es);
+        double tot;
+        if (even)
+            es = block_sum_even<NW>(es, red);
+        tot = even ? es.nu2 : block_sum<NW>(es.nu2, red + 3 * NW);
+        if (!(tot > 0.0) || !isfinite(tot)) {
+            out.status = CFSIM_DEGENERATE;
+            break;
+        }
+        out.nu = sqrt(tot);
+        out.iters = k;
+        const double inv = 1.0 / out.nu;
+        sigma = T(inv);
+        unsigned char* t = Vc;
+        Vc = Vn;
+        Vn = t;
+        if (even) {
+            out.delta = even_step_delta(es, a_even, inv);
+            a_even = inv;
+            if (out.delta < J.tol) {
+                out.status = CFSIM_CONVERGED;
+                break;
+            }
+        } else if (last) {
+            // the last update is odd: U_k stands in Ue and the loop ends
+        }
+    }
+    if (out.status == 0) out.status = CFSIM_HIT_MAX_ITER;
+    return out;
+}
+
+// S = U R^T * inv (M x M) over U (M x m) in place, both from smem: rows are
+// expanded from the last group of NW rows to the first; a group reads its U
+// rows into registers, waits, and writes its S rows, whose bytes only cover
+// U rows at or after their own (M >= m).
+template <typename T, int NT>
+__device__ __forceinline__ void expand_resized(unsigned char* smem, int M, int m, T inv) {
+    constexpr int NW = NT / kWave;
+    constexpr int MCH = 3;  // output chunks of 64 columns: M <= 192
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int wave = (int)threadIdx.x / kWave;
+    T* U = reinterpret_cast<T*>(smem);
+    const int groups = (M + NW - 1) / NW;
+    for (int g = groups - 1; g >= 0; --g) {
+        const int i = g * NW + wave;
+        T o[MCH];
+#pragma unroll
+        for (int c = 0; c < MCH; ++c) {
+            const int q = c * kWave + lane;
+            o[c] = T(0);
+            if (i < M && q < M) {
+                const Interp ip = interp_at(q, m, M);
+                const T* ur = U + (long long)i * m;
+                o[c] = (T(1.0 - ip.f) * ur[ip.r0] + T(ip.f) * ur[ip.r1]) * inv;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < MCH; ++c) {
+            const int q = c * kWave + lane;
+            if (i < M && q < M) U[(long long)i * M + q] = o[c];
+        }
+    }
+    __syncthreads();
 }
 
 // Step a7, rows of at most kSortCols entries: the greedy order itself.  Each
@@ -1114,10 +1327,68 @@ __device__ inline bool refine_skips(const PairJob& J, int p) {
     return !(st & CFSIM_NEAR_TIE) || (st & CFSIM_INVALID_INPUT);
 }
 
-template <typename T, int NT, int NCHMAX, bool DAMPED>
+// A pair of unequal sizes in the resized mode: the larger graph takes the
+// rows (stored S^T when that is A); iteration at M x m, expansion to M x M,
+// matching and outputs at M x M (S_out and match as for the tiled path).
+template <typename T, int NT, int NCHMAX>
+__device__ __forceinline__ void resized_pair(const PairJob& J, int p, const GraphRef& A, const GraphRef& B,
+                                             cfsim_pair_result* res, unsigned char* smem, double* red,
+                                             int* s_count) {
+    constexpr int NW = NT / kWave;
+    const bool swp = B.n < A.n;  // rows = A's nodes: S is stored transposed
+    const GraphRef Lg = pick_graph(swp, A, B);
+    const GraphRef Xg = pick_graph(swp, B, A);
+    const int M = Lg.n, m = Xg.n;
+    const int esz = (int)sizeof(T);
+    if ((m + 63) / 64 > NCHMAX || !resized_fits(M, m, Lg.nnz, Xg.nnz, J.variant, esz)) {
+        if (threadIdx.x == 0) write_invalid(res);
+        return;
+    }
+    PairShape sh{};
+    sh.swap = swp ? 1 : 0;
+    sh.nR = M;
+    sh.nC = m;
+    sh.nchunk = (m + 63) / 64;
+    sh.rows = (M + NW - 1) / NW;
+    const size_t B1 = align16((size_t)M * m * esz);
+    IterOut it;
+    {
+        const Lists<T> G = carve_lists<T>(smem + 3 * B1, M, m, Lg.nnz, Xg.nnz);
+        const bool degenerate = stage_pair<T, NT>(Lg, Xg, M, m, G, reinterpret_cast<T*>(smem), T(0));
+        if (NCHMAX == 1 || sh.nchunk == 1)
+            it = iterate_resized<T, NT, 1>(J, smem, B1, sh, G, degenerate, red);
+        else if (NCHMAX == 2 || sh.nchunk == 2)
+            it = iterate_resized<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, B1, sh, G, degenerate, red);
+        else
+            it = iterate_resized<T, NT, NCHMAX>(J, smem, B1, sh, G, degenerate, red);
+    }
+    const T inv = it.status == CFSIM_DEGENERATE && it.iters == 0 ? T(1) : T(1.0 / it.nu);
+    expand_resized<T, NT>(smem, M, m, inv);
+    const size_t SB = align16((size_t)M * M * esz);
+    PairShape shm = sh;
+    shm.nC = M;
+    shm.nchunk = (M + 63) / 64;
+    const Lists<T> Gm = carve_lists<T>(smem + 2 * SB, M, M, 0, 0);
+    GraphRef Am = A, Bm = B;  // outputs are n_M x n_M
+    Am.n = M;
+    Bm.n = M;
+    match_and_write<T, NT>(J, p, Am, Bm, shm, reinterpret_cast<const T*>(smem), reinterpret_cast<T*>(smem + SB), Gm,
+                           it, res, red, s_count);
+}
+
+template <typename T, int NT, int NCHMAX, int MODE>
 __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count,
                                          int* s_seg) {
     if (refine_skips(J, p)) return;
+    if constexpr (MODE == kModeResized) {
+        GraphRef A{}, B{};
+        cfsim_pair_result* res;
+        if (resolve_graphs(J, p, A, B, res) && A.n != B.n) {
+            resized_pair<T, NT, NCHMAX>(J, p, A, B, res, smem, red, s_count);
+            return;
+        }
+    }
+    constexpr bool DAMPED = MODE == kModeDamped;
     IterOut it;
     {
         GraphRef A{}, B{};
@@ -1176,8 +1447,9 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
     match_and_write<T, NT>(Jr, p, A, B, sh, S, St, G, it, res, red, s_count);
 }
 
-template <typename T, int NT, bool DAMPED>
+template <typename T, int NT, int MODE>
 __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
+    constexpr bool DAMPED = MODE == kModeDamped;
     if (refine_skips(J, p)) return;
     GraphRef A{}, B{};
     cfsim_pair_result* res;
@@ -1214,15 +1486,15 @@ __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned ch
 
 // Persistent driver: one pair at a time per workgroup, pulled from the
 // bucket's queue (or the single pair of the plain path).
-template <bool GLOBAL, typename T, int NT, int NCH, bool DAMPED>
+template <bool GLOBAL, typename T, int NT, int NCH, int MODE>
 __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, double* red, int* s_item, int* s_count,
                                       int* s_seg) {
     if (J.single) {
         if (blockIdx.x == 0) {
             if constexpr (GLOBAL)
-                global_pair<T, NT, DAMPED>(J, 0, smem, red, s_count);
+                global_pair<T, NT, MODE>(J, 0, smem, red, s_count);
             else
-                lds_pair<T, NT, NCH, DAMPED>(J, 0, smem, red, s_count, s_seg);
+                lds_pair<T, NT, NCH, MODE>(J, 0, smem, red, s_count, s_seg);
         }
         return;
     }
@@ -1234,9 +1506,9 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
         __syncthreads();
         if (item >= Jl.bounds[1]) break;
         if constexpr (GLOBAL)
-            global_pair<T, NT, DAMPED>(Jl, Jl.order[item], smem, red, s_count);
+            global_pair<T, NT, MODE>(Jl, Jl.order[item], smem, red, s_count);
         else
-            lds_pair<T, NT, NCH, DAMPED>(Jl, Jl.order[item], smem, red, s_count, s_seg);
+            lds_pair<T, NT, NCH, MODE>(Jl, Jl.order[item], smem, red, s_count, s_seg);
     }
 }
 
@@ -1253,7 +1525,7 @@ void pair_lds_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (NT / kWave)];
     __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
-    drive<false, T, NT, NCH, false>(J, smem, red, &s_item, s_count, s_seg);
+    drive<false, T, NT, NCH, kModePlain>(J, smem, red, &s_item, s_count, s_seg);
 }
 
 // The damped measure on the same variants and schedule.
@@ -1263,7 +1535,17 @@ void damped_lds_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (NT / kWave)];
     __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
-    drive<false, T, NT, NCH, true>(J, smem, red, &s_item, s_count, s_seg);
+    drive<false, T, NT, NCH, kModeDamped>(J, smem, red, &s_item, s_count, s_seg);
+}
+
+// The scale-to-common-size mode on the same variants and schedule.
+template <typename T, int NT, int NCH>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<NT>())))
+void resized_lds_kernel(PairJob J) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4 * (NT / kWave)];
+    __shared__ int s_item, s_count[2], s_seg[kRowClasses + 1];
+    drive<false, T, NT, NCH, kModeResized>(J, smem, red, &s_item, s_count, s_seg);
 }
 
 template <typename T>
@@ -1272,7 +1554,7 @@ void pair_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
     __shared__ int s_item, s_count[2];
-    drive<true, T, kGlobalThreads, 1, false>(J, smem, red, &s_item, s_count, nullptr);
+    drive<true, T, kGlobalThreads, 1, kModePlain>(J, smem, red, &s_item, s_count, nullptr);
 }
 
 template <typename T>
@@ -1281,7 +1563,7 @@ void damped_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
     __shared__ int s_item, s_count[2];
-    drive<true, T, kGlobalThreads, 1, true>(J, smem, red, &s_item, s_count, nullptr);
+    drive<true, T, kGlobalThreads, 1, kModeDamped>(J, smem, red, &s_item, s_count, nullptr);
 }
 
 // Pairs no kernel can take get an INVALID_INPUT result.
@@ -1314,18 +1596,29 @@ __device__ void classify(const PlanJob& P, int64_t p, int* bucket, int* cls) {
     if (nA < 1 || nB < 1) return;
     PairShape sh;
     int b = kBucketInvalid;
-    for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
-        if (choose_shape(nA, nB, mA, mB, v, P.esize, &sh)) b = v;
-    if (b < kNumVariants) {  // a tuned larger variant for the pair's class, if it holds the pair
-        const int t = P.tune[tune_class(nA, nB)];
-        if (t > b && t < kNumVariants && choose_shape(nA, nB, mA, mB, t, P.esize, &sh)) b = t;
+    if (P.resize && nA != nB) {
+        // resized mode: the first LDS variant that holds the resized pair; the
+        // rest stay in the invalid bucket and take the tiled path
+        const int M = nA > nB ? nA : nB, m = nA > nB ? nB : nA;
+        const int nnzL = nA > nB ? mA : mB, nnzX = nA > nB ? mB : mA;
+        for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
+            if (resized_fits(M, m, nnzL, nnzX, v, P.esize)) b = v;
+    } else {
+        for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
+            if (choose_shape(nA, nB, mA, mB, v, P.esize, &sh)) b = v;
+        if (b < kNumVariants) {  // a tuned larger variant for the pair's class, if it holds the pair
+            const int t = P.tune[tune_class(nA, nB)];
+            if (t > b && t < kNumVariants && choose_shape(nA, nB, mA, mB, t, P.esize, &sh)) b = t;
+        }
+        if (b == kBucketInvalid && !P.resize && global_fits(nA, nB, mA, mB, P.esize, P.slot_elems, &sh))
+            b = kBucketGlobal;
     }
-    if (b == kBucketInvalid && global_fits(nA, nB, mA, mB, P.esize, P.slot_elems, &sh)) b = kBucketGlobal;
     if (P.filter && b == kBucketInvalid) {  // no FP64 kernel holds it: the FP32 result stays
         *bucket = -1;
         return;
     }
-    // longest first: cost class from log2 of the work estimate
+    // longest first: cost class from log2 of the work estimate (the resized
+    // state is M x m, the iteration's shape either way)
     const double work = (double)nA * (double)nB * (1.0 + (double)(mA + mB) / (double)(nA + nB + 1));
     int c = (int)(4.0 * log2(work > 1.0 ? work : 1.0));
     c = c < 0 ? 0 : (c >= kClasses ? kClasses - 1 : c);
@@ -1376,36 +1669,39 @@ __global__ __launch_bounds__(256) void buckets_kernel(PlanJob P, int32_t* bucket
 }
 
 template <typename T, int NT, int NCH>
-const void* kernel_ptr(bool damped) {
-    return damped ? reinterpret_cast<const void*>(&damped_lds_kernel<T, NT, NCH>)
-                  : reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
+const void* kernel_ptr(int mode) {
+    return mode == kModeDamped    ? reinterpret_cast<const void*>(&damped_lds_kernel<T, NT, NCH>)
+           : mode == kModeResized ? reinterpret_cast<const void*>(&resized_lds_kernel<T, NT, NCH>)
+                                  : reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
 }
 
+// The resized mode has no global-memory kernel (its pairs beyond LDS take the
+// tiled path); its bucket 5 is always empty and runs the plain kernel.
 template <typename T>
-const void* global_kernel_ptr(bool damped) {
-    return damped ? reinterpret_cast<const void*>(&damped_global_kernel<T>)
-                  : reinterpret_cast<const void*>(&pair_global_kernel<T>);
+const void* global_kernel_ptr(int mode) {
+    return mode == kModeDamped ? reinterpret_cast<const void*>(&damped_global_kernel<T>)
+                               : reinterpret_cast<const void*>(&pair_global_kernel<T>);
 }
 
 // Instantiations must match variant_info().
-const void* variant_kernel(int v, int dtype, bool damped = false) {
+const void* variant_kernel(int v, int dtype, int mode = kModePlain) {
     if (v == kBucketGlobal)
-        return dtype == CFSIM_F64 ? global_kernel_ptr<double>(damped) : global_kernel_ptr<float>(damped);
+        return dtype == CFSIM_F64 ? global_kernel_ptr<double>(mode) : global_kernel_ptr<float>(mode);
     if (dtype == CFSIM_F64) {
         switch (v) {
-            case 0: return kernel_ptr<double, 64, 1>(damped);
-            case 1: return kernel_ptr<double, 256, 2>(damped);
-            case 2: return kernel_ptr<double, 512, 2>(damped);
-            case 3: return kernel_ptr<double, 1024, 2>(damped);
-            default: return kernel_ptr<double, 1024, 4>(damped);
+            case 0: return kernel_ptr<double, 64, 1>(mode);
+            case 1: return kernel_ptr<double, 256, 2>(mode);
+            case 2: return kernel_ptr<double, 512, 2>(mode);
+            case 3: return kernel_ptr<double, 1024, 2>(mode);
+            default: return kernel_ptr<double, 1024, 4>(mode);
         }
     }
     switch (v) {
-        case 0: return kernel_ptr<float, 64, 2>(damped);
-        case 1: return kernel_ptr<float, 256, 4>(damped);
-        case 2: return kernel_ptr<float, 512, 2>(damped);
-        case 3: return kernel_ptr<float, 1024, 2>(damped);
-        default: return kernel_ptr<float, 1024, 4>(damped);
+        case 0: return kernel_ptr<float, 64, 2>(mode);
+        case 1: return kernel_ptr<float, 256, 4>(mode);
+        case 2: return kernel_ptr<float, 512, 2>(mode);
+        case 3: return kernel_ptr<float, 1024, 2>(mode);
+        default: return kernel_ptr<float, 1024, 4>(mode);
     }
 }
 
@@ -1421,7 +1717,8 @@ int launch_pair_lds(int variant, int dtype, const PairJob& job, int grid, hipStr
     }
     const int esize = dtype == CFSIM_F64 ? 8 : 4;
     void* args[] = {const_cast<PairJob*>(&job)};
-    return (int)hipLaunchKernel(variant_kernel(variant, dtype, job.damped != 0), dim3(grid),
+    const int mode = job.damped ? kModeDamped : (job.resize ? kModeResized : kModePlain);
+    return (int)hipLaunchKernel(variant_kernel(variant, dtype, mode), dim3(grid),
                                 dim3(threads_of(variant, esize)), args,
                                 (size_t)lds_of(variant, esize), stream);
 }
@@ -1453,10 +1750,10 @@ const char* bucket_kernel_name(int bucket, int dtype) {
 int set_kernel_attributes() {
     int e = 0;
     for (int v = 0; v <= kBucketGlobal; ++v)
-        for (int damped = 0; damped < 2; ++damped) {
-            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F32, damped != 0),
+        for (int mode = kModePlain; mode <= kModeResized; ++mode) {
+            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F32, mode),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_of(v, 4));
-            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F64, damped != 0),
+            e |= (int)hipFuncSetAttribute(variant_kernel(v, CFSIM_F64, mode),
                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds_of(v, 8));
         }
     return e;

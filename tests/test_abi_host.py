@@ -247,7 +247,9 @@ def test_resize_limits_and_unsupported_calls():
     assert "8192" in L.cfsim_last_error().decode()
     assert L.cfsim_batch_workspace_size(None, ctypes.byref(s), 5, ctypes.byref(opt)) == 0
     s = _set()
-    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None) == -6
+    # resized calls have buckets (LDS kernels in their resized mode, the rest on the tiled path)
+    assert L.cfsim_batch_buckets(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, None) == -1
+    assert "context" in L.cfsim_last_error().decode()
     assert L.cfsim_score_backward(None, ctypes.byref(s), 0x1000, 0x1000, 5, ctypes.byref(opt), 0x1000, 0x1000,
                                   0x1000, 0x1000, 0x1000, None, 8, None, None, 0x1000, 1 << 40, None) == -6
     opt_long = cf.options("f32", max_iter=5000, resize="bilinear")

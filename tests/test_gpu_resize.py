@@ -122,3 +122,48 @@ def test_resize_batch_fp64_agrees_with_plain_and_replays(cf, ctx):
         b.run()
         torch.cuda.synchronize()
         assert b.results().tobytes() == r1 and torch.equal(b.S, S1)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_resized_batch_routes_lds_and_tiled_pairs(cf, ctx, dtype):
+    """Pairs the LDS kernels hold in their resized mode (M x m state, M x M
+    matching) and pairs left to the tiled path, in one call, against the
+    oracle; equal sizes, a one-node graph and a degenerate graph included."""
+    sizes = [128, 120, 9, 64, 37, 100, 1, 5, 77]
+    graphs = _graphs(sizes, seed=33)
+    graphs.append(CFG(6, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([0.0, 0.0])))
+    pa = np.array([0, 0, 2, 3, 4, 5, 6, 7, 8, 9, 3, 4, 8], np.int32)
+    pb = np.array([1, 2, 3, 4, 5, 1, 7, 3, 0, 2, 3, 8, 4], np.int32)
+    gs = cf.pack(ctx, graphs)
+    b = cf.Batch(ctx, gs, pa, pb, dtype=dtype, resize="bilinear", want_S=True)
+    buckets = b.buckets()
+    assert buckets[0] == cf.NUM_BUCKETS - 1          # 128 x 120: beyond LDS, tiled path
+    lds = buckets < cf.NUM_BUCKETS - 2
+    if dtype == "f32":
+        assert lds[1:].all()                         # the rest on the LDS kernels
+    else:                                            # FP64: M x M matching beyond ~99 nodes is tiled
+        assert lds.sum() >= 8 and (~lds).sum() >= 2
+    b.run()
+    torch.cuda.synchronize()
+    res, ms, Ss = b.results(), b.matches(), b.S_list()
+    for p in range(len(pa)):
+        ref = oracle_pair(graphs, int(pa[p]), int(pb[p]), resize="bilinear")
+        assert Ss[p].shape == ref.S.shape
+        if dtype == "f64":
+            assert res["iters"][p] == ref.iters and base_status(res["status"][p]) == ref.status, p
+        er = check_S(Ss[p], ref.S, dtype)
+        check_margin(res["margin"][p], Ss[p], ms[p], dtype)
+        check_matching(Ss[p], ms[p], ref.S, dtype, er)
+
+
+@pytest.mark.parametrize("max_iter,tol", [(1, 1e-12), (2, 1e-12), (3, 0.0), (8, 0.0), (200, 1e-4)])
+def test_resized_batch_iteration_controls(cf, ctx, max_iter, tol):
+    graphs = _graphs([20, 37, 64, 9], seed=17)
+    pa = np.array([1, 2, 3], np.int32)
+    pb = np.array([0, 1, 2], np.int32)
+    gs = cf.pack(ctx, graphs)
+    res, ms, Ss = cf.score_batch(ctx, gs, pa, pb, dtype="f64", max_iter=max_iter, tol=tol, resize="bilinear",
+                                 want_S=True)
+    for p in range(len(pa)):
+        ref = oracle_pair(graphs, int(pa[p]), int(pb[p]), max_iter, tol, resize="bilinear")
+        _check(Ss[p], ms[p], res[p], ref, "f64")
