@@ -219,6 +219,11 @@ size_t batch_ws_bytes(const cfsim_context* ctx, int64_t n_pairs, int esize, int 
     for (int v = 0; v <= cfsim::kBucketGlobal; ++v) b += slot_bytes(ctx, v, esize, max_nodes);
     return b;
 }
+// Global-memory slots of the resized mode's global kernel (one per workgroup).
+size_t resized_slots_bytes(const cfsim_context* ctx, int esize, int max_nodes) {
+    const size_t wgs = (size_t)num_cus_of(ctx) * (size_t)lds_blocks_per_cu(cfsim::kBucketGlobal, esize);
+    return align256(wgs * cfsim::resized_slot_bytes(cfsim::resized_slot_elems(max_nodes), esize));
+}
 // The schedule part of the batch workspace alone (order, bounds, queues).
 size_t sched_ws_bytes(int64_t n_pairs) {
     return align256((size_t)n_pairs * 4) + align256(2 * cfsim::kBuckets * 4) + align256(cfsim::kBuckets * 4);
@@ -683,7 +688,7 @@ size_t cfsim_batch_workspace_size(const cfsim_context* ctx, const cfsim_graph_se
         if (set->max_nodes > cfsim::kLargeMaxNodes) return 0;
         // the tiled path's workspace, then the LDS kernels' schedule
         return large_ws_bytes(n_pairs > 0 ? n_pairs : 1, set->max_nodes, esize_of(opt->dtype), 6) +
-               sched_ws_bytes(n_pairs);
+               sched_ws_bytes(n_pairs) + resized_slots_bytes(ctx, esize_of(opt->dtype), set->max_nodes);
     }
     return batch_ws_bytes(ctx, n_pairs, fp64_final(opt) ? 8 : esize_of(opt->dtype), set->max_nodes);
 }
@@ -719,7 +724,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
     plan.n_pairs = n_pairs;
     plan.filter = filter;
     plan.esize = esize;
-    plan.slot_elems = global_slot_elems(set->max_nodes);
+    plan.slot_elems = resize ? cfsim::resized_slot_elems(set->max_nodes) : global_slot_elems(set->max_nodes);
     plan.order = b.order;
     plan.bounds = b.bounds;
     plan.queues = b.queues;
@@ -766,7 +771,7 @@ static int enqueue_pass(cfsim_context* ctx, const cfsim_graph_set* set, const in
             grid = ctx->grid[d][v];
         } else if (v == cfsim::kBucketGlobal) {
             job.gws = b.slots[v];
-            job.slot_elems = global_slot_elems(set->max_nodes);
+            job.slot_elems = resize ? cfsim::resized_slot_elems(set->max_nodes) : global_slot_elems(set->max_nodes);
             grid = ctx->grid[d][v];
         }
         if (timed && (e = (int)hipEventRecord(ctx->t0[v], st)) != 0) return e;
@@ -811,7 +816,8 @@ static int enqueue_resized(cfsim_context* ctx, const cfsim_graph_set* set, const
                            int32_t* match, const int64_t* match_off, void* S_out, const int64_t* S_off, void* ws,
                            hipStream_t st) {
     const size_t lb = large_ws_bytes(n_pairs, set->max_nodes, esize_of(opt->dtype), 6);
-    const BatchWs b = carve_sched(static_cast<unsigned char*>(ws) + lb, n_pairs);
+    BatchWs b = carve_sched(static_cast<unsigned char*>(ws) + lb, n_pairs);
+    b.slots[cfsim::kBucketGlobal] = static_cast<unsigned char*>(ws) + lb + sched_ws_bytes(n_pairs);
     int e = enqueue_pass(ctx, set, pair_a, pair_b, n_pairs, opt, opt->dtype, nullptr, res, match, match_off, S_out,
                          S_off, b, st, false, CkptOut{nullptr, nullptr, 0}, Damping{0, 0.0, nullptr, nullptr}, 1);
     if (e != 0) return e;

@@ -228,6 +228,23 @@ __host__ __device__ inline size_t resized_iter_bytes(int M, int m, int nnzR, int
 __host__ __device__ inline size_t resized_match_bytes(int M, int esize) {
     return 2 * align16((size_t)M * M * esize) + lds_lists_bytes(M, M, 0, 0, esize);
 }
+// Resized pairs beyond every LDS variant: one 512-thread workgroup per pair
+// with U_even, V_a, V_b (and then S, S^T) in a global-memory slot of
+// 3 * align16(slot_elems * esize) bytes, slot_elems = min(max_nodes, 256)^2,
+// the lists in LDS; the smaller graph at most two 64-column chunks.
+constexpr int kResizedGlobalMax = 256;
+__host__ __device__ inline long long resized_slot_elems(int max_nodes) {
+    const long long n = max_nodes < kResizedGlobalMax ? max_nodes : kResizedGlobalMax;
+    return n * n;
+}
+__host__ __device__ inline size_t resized_slot_bytes(long long slot_elems, int esize) {
+    return 3 * align16((size_t)slot_elems * esize);
+}
+__host__ __device__ inline bool resized_global_fits(int M, int m, int nnzR, int nnzC, int esize, long long slot_elems) {
+    return m <= 2 * 64 && (long long)M * M <= slot_elems &&
+           lds_lists_bytes(M, m, nnzR, nnzC, esize) <= (size_t)kGlobalLds &&
+           lds_lists_bytes(M, M, 0, 0, esize) <= (size_t)kGlobalLds;
+}
 __host__ __device__ inline bool resized_fits(int M, int m, int nnzR, int nnzC, int variant, int esize) {
     const Variant v = variant_info(variant, esize);
     if ((m + 63) / 64 > v.nch) return false;

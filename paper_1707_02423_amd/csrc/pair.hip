@@ -835,7 +835,7 @@ __device__ __forceinline__ IterOut iterate_resized(const PairJob& J, unsigned ch
 template <typename T, int NT>
 __device__ __forceinline__ void expand_resized(unsigned char* smem, int M, int m, T inv) {
     constexpr int NW = NT / kWave;
-    constexpr int MCH = 3;  // output chunks of 64 columns: M <= 192
+    constexpr int MCH = 4;  // output chunks of 64 columns: M <= 256 (the LDS and global fits ensure it)
     const int lane = (int)(threadIdx.x & (kWave - 1));
     const int wave = (int)threadIdx.x / kWave;
     T* U = reinterpret_cast<T*>(smem);
@@ -1330,7 +1330,7 @@ __device__ inline bool refine_skips(const PairJob& J, int p) {
 // A pair of unequal sizes in the resized mode: the larger graph takes the
 // rows (stored S^T when that is A); iteration at M x m, expansion to M x M,
 // matching and outputs at M x M (S_out and match as for the tiled path).
-template <typename T, int NT, int NCHMAX>
+template <typename T, int NT, int NCHMAX, bool GLOBAL>
 __device__ __forceinline__ void resized_pair(const PairJob& J, int p, const GraphRef& A, const GraphRef& B,
                                              cfsim_pair_result* res, unsigned char* smem, double* red,
                                              int* s_count) {
@@ -1340,10 +1340,16 @@ __device__ __forceinline__ void resized_pair(const PairJob& J, int p, const Grap
     const GraphRef Xg = pick_graph(swp, B, A);
     const int M = Lg.n, m = Xg.n;
     const int esz = (int)sizeof(T);
-    if ((m + 63) / 64 > NCHMAX || !resized_fits(M, m, Lg.nnz, Xg.nnz, J.variant, esz)) {
+    const bool fits = GLOBAL ? resized_global_fits(M, m, Lg.nnz, Xg.nnz, esz, J.slot_elems)
+                             : resized_fits(M, m, Lg.nnz, Xg.nnz, J.variant, esz);
+    if ((m + 63) / 64 > NCHMAX || !fits) {
         if (threadIdx.x == 0) write_invalid(res);
         return;
     }
+    // the iterates and then S, S^T: LDS, or this workgroup's global slot
+    unsigned char* buf =
+        GLOBAL ? reinterpret_cast<unsigned char*>(J.gws) + (size_t)blockIdx.x * resized_slot_bytes(J.slot_elems, esz)
+               : smem;
     PairShape sh{};
     sh.swap = swp ? 1 : 0;
     sh.nR = M;
@@ -1353,26 +1359,26 @@ __device__ __forceinline__ void resized_pair(const PairJob& J, int p, const Grap
     const size_t B1 = align16((size_t)M * m * esz);
     IterOut it;
     {
-        const Lists<T> G = carve_lists<T>(smem + 3 * B1, M, m, Lg.nnz, Xg.nnz);
-        const bool degenerate = stage_pair<T, NT>(Lg, Xg, M, m, G, reinterpret_cast<T*>(smem), T(0));
+        const Lists<T> G = carve_lists<T>(GLOBAL ? smem : smem + 3 * B1, M, m, Lg.nnz, Xg.nnz);
+        const bool degenerate = stage_pair<T, NT>(Lg, Xg, M, m, G, reinterpret_cast<T*>(buf), T(0));
         if (NCHMAX == 1 || sh.nchunk == 1)
-            it = iterate_resized<T, NT, 1>(J, smem, B1, sh, G, degenerate, red);
+            it = iterate_resized<T, NT, 1>(J, buf, B1, sh, G, degenerate, red);
         else if (NCHMAX == 2 || sh.nchunk == 2)
-            it = iterate_resized<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, smem, B1, sh, G, degenerate, red);
+            it = iterate_resized<T, NT, (NCHMAX >= 2 ? 2 : 1)>(J, buf, B1, sh, G, degenerate, red);
         else
-            it = iterate_resized<T, NT, NCHMAX>(J, smem, B1, sh, G, degenerate, red);
+            it = iterate_resized<T, NT, NCHMAX>(J, buf, B1, sh, G, degenerate, red);
     }
     const T inv = it.status == CFSIM_DEGENERATE && it.iters == 0 ? T(1) : T(1.0 / it.nu);
-    expand_resized<T, NT>(smem, M, m, inv);
+    expand_resized<T, NT>(buf, M, m, inv);
     const size_t SB = align16((size_t)M * M * esz);
     PairShape shm = sh;
     shm.nC = M;
     shm.nchunk = (M + 63) / 64;
-    const Lists<T> Gm = carve_lists<T>(smem + 2 * SB, M, M, 0, 0);
+    const Lists<T> Gm = carve_lists<T>(GLOBAL ? smem : smem + 2 * SB, M, M, 0, 0);
     GraphRef Am = A, Bm = B;  // outputs are n_M x n_M
     Am.n = M;
     Bm.n = M;
-    match_and_write<T, NT>(J, p, Am, Bm, shm, reinterpret_cast<const T*>(smem), reinterpret_cast<T*>(smem + SB), Gm,
+    match_and_write<T, NT>(J, p, Am, Bm, shm, reinterpret_cast<const T*>(buf), reinterpret_cast<T*>(buf + SB), Gm,
                            it, res, red, s_count);
 }
 
@@ -1384,7 +1390,7 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
         GraphRef A{}, B{};
         cfsim_pair_result* res;
         if (resolve_graphs(J, p, A, B, res) && A.n != B.n) {
-            resized_pair<T, NT, NCHMAX>(J, p, A, B, res, smem, red, s_count);
+            resized_pair<T, NT, NCHMAX, false>(J, p, A, B, res, smem, red, s_count);
             return;
         }
     }
@@ -1447,9 +1453,18 @@ __device__ __forceinline__ void lds_pair(const PairJob& J, int p, unsigned char*
     match_and_write<T, NT>(Jr, p, A, B, sh, S, St, G, it, res, red, s_count);
 }
 
-template <typename T, int NT, int MODE>
+template <typename T, int NT, int NCH, int MODE>
 __device__ __forceinline__ void global_pair(const PairJob& J, int p, unsigned char* smem, double* red, int* s_count) {
     constexpr bool DAMPED = MODE == kModeDamped;
+    if constexpr (MODE == kModeResized) {
+        GraphRef A{}, B{};
+        cfsim_pair_result* res;
+        if (refine_skips(J, p)) return;
+        if (resolve_graphs(J, p, A, B, res) && A.n != B.n) {
+            resized_pair<T, NT, NCH, true>(J, p, A, B, res, smem, red, s_count);
+            return;
+        }
+    }
     if (refine_skips(J, p)) return;
     GraphRef A{}, B{};
     cfsim_pair_result* res;
@@ -1492,7 +1507,7 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
     if (J.single) {
         if (blockIdx.x == 0) {
             if constexpr (GLOBAL)
-                global_pair<T, NT, MODE>(J, 0, smem, red, s_count);
+                global_pair<T, NT, NCH, MODE>(J, 0, smem, red, s_count);
             else
                 lds_pair<T, NT, NCH, MODE>(J, 0, smem, red, s_count, s_seg);
         }
@@ -1506,7 +1521,7 @@ __device__ __forceinline__ void drive(const PairJob& J, unsigned char* smem, dou
         __syncthreads();
         if (item >= Jl.bounds[1]) break;
         if constexpr (GLOBAL)
-            global_pair<T, NT, MODE>(Jl, Jl.order[item], smem, red, s_count);
+            global_pair<T, NT, NCH, MODE>(Jl, Jl.order[item], smem, red, s_count);
         else
             lds_pair<T, NT, NCH, MODE>(Jl, Jl.order[item], smem, red, s_count, s_seg);
     }
@@ -1559,6 +1574,15 @@ void pair_global_kernel(PairJob J) {
 
 template <typename T>
 __global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void resized_global_kernel(PairJob J) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[4 * (kGlobalThreads / kWave)];
+    __shared__ int s_item, s_count[2];
+    drive<true, T, kGlobalThreads, 2, kModeResized>(J, smem, red, &s_item, s_count, nullptr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kGlobalThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void damped_global_kernel(PairJob J) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[4 * (kGlobalThreads / kWave)];
@@ -1597,12 +1621,14 @@ __device__ void classify(const PlanJob& P, int64_t p, int* bucket, int* cls) {
     PairShape sh;
     int b = kBucketInvalid;
     if (P.resize && nA != nB) {
-        // resized mode: the first LDS variant that holds the resized pair; the
-        // rest stay in the invalid bucket and take the tiled path
+        // resized mode: the first LDS variant that holds the resized pair, else
+        // the global-memory kernel; the rest stay in the invalid bucket and
+        // take the tiled path
         const int M = nA > nB ? nA : nB, m = nA > nB ? nB : nA;
         const int nnzL = nA > nB ? mA : mB, nnzX = nA > nB ? mB : mA;
         for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
             if (resized_fits(M, m, nnzL, nnzX, v, P.esize)) b = v;
+        if (b == kBucketInvalid && resized_global_fits(M, m, nnzL, nnzX, P.esize, P.slot_elems)) b = kBucketGlobal;
     } else {
         for (int v = 0; v < kNumVariants && b == kBucketInvalid; ++v)
             if (choose_shape(nA, nB, mA, mB, v, P.esize, &sh)) b = v;
@@ -1675,12 +1701,11 @@ const void* kernel_ptr(int mode) {
                                   : reinterpret_cast<const void*>(&pair_lds_kernel<T, NT, NCH>);
 }
 
-// The resized mode has no global-memory kernel (its pairs beyond LDS take the
-// tiled path); its bucket 5 is always empty and runs the plain kernel.
 template <typename T>
 const void* global_kernel_ptr(int mode) {
-    return mode == kModeDamped ? reinterpret_cast<const void*>(&damped_global_kernel<T>)
-                               : reinterpret_cast<const void*>(&pair_global_kernel<T>);
+    return mode == kModeDamped    ? reinterpret_cast<const void*>(&damped_global_kernel<T>)
+           : mode == kModeResized ? reinterpret_cast<const void*>(&resized_global_kernel<T>)
+                                  : reinterpret_cast<const void*>(&pair_global_kernel<T>);
 }
 
 // Instantiations must match variant_info().

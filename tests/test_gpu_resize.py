@@ -125,24 +125,27 @@ def test_resize_batch_fp64_agrees_with_plain_and_replays(cf, ctx):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_resized_batch_routes_lds_and_tiled_pairs(cf, ctx, dtype):
-    """Pairs the LDS kernels hold in their resized mode (M x m state, M x M
-    matching) and pairs left to the tiled path, in one call, against the
-    oracle; equal sizes, a one-node graph and a degenerate graph included."""
-    sizes = [128, 120, 9, 64, 37, 100, 1, 5, 77]
+def test_resized_batch_routes_lds_global_and_tiled_pairs(cf, ctx, dtype):
+    """One call with pairs the LDS kernels hold in their resized mode (M x m
+    state, M x M matching), pairs beyond LDS for the global-memory kernel
+    (state and S in a workspace slot) and pairs for the tiled path (smaller
+    graph over 128 nodes), against the oracle; equal sizes, a one-node graph
+    and a degenerate graph included."""
+    sizes = [128, 120, 9, 64, 37, 100, 1, 5, 77, 200, 150]
     graphs = _graphs(sizes, seed=33)
     graphs.append(CFG(6, np.array([0, 1], np.int32), np.array([1, 2], np.int32), np.array([0.0, 0.0])))
-    pa = np.array([0, 0, 2, 3, 4, 5, 6, 7, 8, 9, 3, 4, 8], np.int32)
-    pb = np.array([1, 2, 3, 4, 5, 1, 7, 3, 0, 2, 3, 8, 4], np.int32)
+    pa = np.array([0, 9, 0, 2, 3, 4, 5, 6, 7, 8, 11, 3, 4, 8], np.int32)
+    pb = np.array([1, 10, 2, 3, 4, 5, 1, 7, 3, 0, 2, 3, 8, 4], np.int32)
     gs = cf.pack(ctx, graphs)
     b = cf.Batch(ctx, gs, pa, pb, dtype=dtype, resize="bilinear", want_S=True)
     buckets = b.buckets()
-    assert buckets[0] == cf.NUM_BUCKETS - 1          # 128 x 120: beyond LDS, tiled path
+    assert buckets[0] == cf.NUM_BUCKETS - 2          # 128 x 120: the global-memory kernel
+    assert buckets[1] == cf.NUM_BUCKETS - 1          # 200 x 150: the tiled path
     lds = buckets < cf.NUM_BUCKETS - 2
     if dtype == "f32":
-        assert lds[1:].all()                         # the rest on the LDS kernels
-    else:                                            # FP64: M x M matching beyond ~99 nodes is tiled
-        assert lds.sum() >= 8 and (~lds).sum() >= 2
+        assert lds[2:].all()                         # the rest on the LDS kernels
+    else:                                            # FP64: M x M matching beyond ~99 nodes is not in LDS
+        assert lds.sum() >= 8
     b.run()
     torch.cuda.synchronize()
     res, ms, Ss = b.results(), b.matches(), b.S_list()
