@@ -211,9 +211,11 @@ cfsim_status cfsim_pack(cfsim_context* ctx, int32_t n_graphs, int64_t total_node
  * match_out may be NULL.  With opt->resize = CFSIM_RESIZE_BILINEAR
  * (Section 4 and Section 4.1: the smaller transition matrix X becomes
  * R X R^T with the order-1 interpolation R from its m nodes to n_M points
- * at p (m - 1) / (n_M - 1)) the pair runs on the tiled path of
- * cfsim_score_large (a short launch sequence instead of one launch) and
- * needs n_M <= 8192 and max_iter <= 4096.
+ * at p (m - 1) / (n_M - 1)) a pair of unequal sizes runs in the resized
+ * mode of an LDS kernel when one holds it (one launch: the operator in
+ * factored form at n_M x m, then S at n_M x n_M), else on the tiled path of
+ * cfsim_score_large (a short launch sequence; n_M <= 8192 and max_iter <=
+ * 4096); a pair of equal sizes needs no scaling and runs as without resize.
  */
 size_t cfsim_score_workspace_size(const cfsim_context* ctx, int32_t n_a, int32_t n_b,
                                   const cfsim_options* opt);

@@ -601,8 +601,12 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
     if ((s = check_no_mfma(opt)) != CFSIM_OK) return s;
     if (!res) return fail(CFSIM_E_INVALID_ARG, "res is NULL");
     const int esize = esize_of(opt->dtype);
-    if (opt->resize == CFSIM_RESIZE_BILINEAR) {
-        // scaled pairs run on the tiled path (the resized operator in factored form)
+    if (opt->resize == CFSIM_RESIZE_BILINEAR && A->n == B->n && fp64_final(opt))
+        return check_no_fp64_final(opt);
+    if (opt->resize == CFSIM_RESIZE_BILINEAR && A->n != B->n) {
+        // scaled pairs: the resized mode of an LDS kernel when one holds the
+        // pair (one launch), else the tiled path (the same factored operator);
+        // equal sizes need no scaling and take the plain path below
         const int M = A->n > B->n ? A->n : B->n;
         if ((s = check_no_fp64_final(opt)) != CFSIM_OK) return s;
         if ((s = check_large_limits(M, opt)) != CFSIM_OK) return s;
@@ -610,6 +614,34 @@ cfsim_status cfsim_score(cfsim_context* ctx, const cfsim_graph* A, const cfsim_g
         if (ws_bytes < need || !ws)
             return fail(CFSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
         if (!ctx) return fail(CFSIM_E_INVALID_ARG, "context is NULL");
+        {
+            const bool a_larger = A->n > B->n;
+            const int m = a_larger ? B->n : A->n;
+            const int nnzL = a_larger ? A->nnz : B->nnz, nnzX = a_larger ? B->nnz : A->nnz;
+            // the widest workgroup first: a lone pair waits on a barrier every update
+            int v = -1;
+            for (int c : {3, 4, 2, 1, 0})
+                if (v < 0 && cfsim::resized_fits(M, m, nnzL, nnzX, c, esize)) v = c;
+            if (v >= 0) {
+                cfsim::PairJob job{};
+                job.single = 1;
+                job.ga = ref_of(A);
+                job.gb = ref_of(B);
+                job.max_iter = opt->max_iter;
+                job.tol = opt->tol;
+                job.tie_tol = tie_tol_of(opt, opt->dtype);
+                job.res = res;
+                job.match = match_out;
+                job.S_out = S_out;
+                job.variant = v;
+                job.resize = 1;
+                int e = (int)hipSetDevice(ctx->device);
+                if (e != 0) return hip_fail(e, "hipSetDevice");
+                e = cfsim::launch_pair_lds(v, opt->dtype, job, 1, static_cast<hipStream_t>(stream));
+                if (e != 0) return hip_fail(e, "resized pair kernel launch");
+                return ok();
+            }
+        }
         cfsim::LargeJob J = large_job(opt, 1, M, res, match_out, nullptr, S_out, nullptr, ws);
         J.single = 1;
         J.ga = ref_of(A);
