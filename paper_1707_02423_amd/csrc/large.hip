@@ -42,6 +42,7 @@ using dev::uni;
 using dev::wave_sum;
 
 constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
+constexpr int kReduceGrid = 2048;               // workgroups of the per-pair reduction
 constexpr int kFinishThreads = 1024;
 constexpr int kLS = 2;                          // successors per lane column in registers
 constexpr int kLP = 3;                          // predecessors per lane column in registers
@@ -213,59 +214,64 @@ __global__ __launch_bounds__(256) void large_tile_map(LargeJob J) {
 // delta_{k-1} were accumulated (odd k >= 3).
 __global__ __launch_bounds__(kStepThreads) void large_reduce(LargeJob J, int k) {
     __shared__ double red[2 * kNWStep];
-    const int p = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-    LargeState* s = J.st + p;
-    if (!s->active) return;
     const bool compute = k <= J.max_iter;
     const bool want_delta = (k & 1) && k >= 3;
-    const long long t0 = J.tile_off[p], nt = s->ntiles;
-    double a = 0.0, b = 0.0;
-    for (long long q = tid; q < nt; q += kStepThreads) {
-        a += J.part_nu[t0 + q];
-        b += J.part_delta[t0 + q];
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) {
-        red[wave] = a;
-        red[kNWStep + wave] = b;
-    }
-    __syncthreads();
-    if (tid != 0) return;
-    double nu2s = 0.0, d2s = 0.0;
-    for (int w = 0; w < kNWStep; ++w) {
-        nu2s += red[w];
-        d2s += red[kNWStep + w];
-    }
-    bool stop = false;
-    if (want_delta) {
-        const double delta = sqrt(d2s);
-        s->delta = delta;
-        if (delta < J.tol) {   // converged at the even step k - 1
-            s->final_step = k - 1;
-            s->nu = s->nu_k[(k - 1) & 3];
-            s->status = CFSIM_CONVERGED;
-            stop = true;
+    // pairs in a grid-stride loop: a call whose pairs mostly ran elsewhere
+    // (resized batches) launches a few workgroups instead of one per pair
+    for (int p = blockIdx.x; p < J.n_pairs; p += gridDim.x) {
+        LargeState* s = J.st + p;
+        if (!s->active) continue;  // the same word in every thread
+        const long long t0 = J.tile_off[p], nt = s->ntiles;
+        double a = 0.0, b = 0.0;
+        for (long long q = tid; q < nt; q += kStepThreads) {
+            a += J.part_nu[t0 + q];
+            b += J.part_delta[t0 + q];
         }
-    }
-    if (!stop && compute) {
-        const double nu = sqrt(nu2s);
-        s->nu_k[k & 3] = nu;
-        if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
-            s->final_step = k;
-            s->nu = nu;
-            s->status = CFSIM_HIT_MAX_ITER;
-            stop = true;
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) {
+            red[wave] = a;
+            red[kNWStep + wave] = b;
         }
+        __syncthreads();
+        if (tid == 0) {
+            double nu2s = 0.0, d2s = 0.0;
+            for (int w = 0; w < kNWStep; ++w) {
+                nu2s += red[w];
+                d2s += red[kNWStep + w];
+            }
+            bool stop = false;
+            if (want_delta) {
+                const double delta = sqrt(d2s);
+                s->delta = delta;
+                if (delta < J.tol) {   // converged at the even step k - 1
+                    s->final_step = k - 1;
+                    s->nu = s->nu_k[(k - 1) & 3];
+                    s->status = CFSIM_CONVERGED;
+                    stop = true;
+                }
+            }
+            if (!stop && compute) {
+                const double nu = sqrt(nu2s);
+                s->nu_k[k & 3] = nu;
+                if (k == J.max_iter && (k & 1)) {  // odd max_iter: no change test at k
+                    s->final_step = k;
+                    s->nu = nu;
+                    s->status = CFSIM_HIT_MAX_ITER;
+                    stop = true;
+                }
+            }
+            if (!stop && !compute) {               // launch max_iter + 1
+                s->final_step = J.max_iter;
+                s->nu = s->nu_k[J.max_iter & 3];
+                s->status = CFSIM_HIT_MAX_ITER;
+                stop = true;
+            }
+            if (stop) s->active = 0;
+        }
+        __syncthreads();  // red is reused by the next pair
     }
-    if (!stop && !compute) {               // launch max_iter + 1
-        s->final_step = J.max_iter;
-        s->nu = s->nu_k[J.max_iter & 3];
-        s->status = CFSIM_HIT_MAX_ITER;
-        stop = true;
-    }
-    if (stop) s->active = 0;
 }
 
 // Sum over a row's NS successor and NP predecessor terms (wave-uniform rows u
@@ -1049,7 +1055,8 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
         if ((e = launch_mfma_prep(J, stream)) != 0) return e;
         for (int k = 1; k <= J.max_iter + 1; ++k) {
             if ((e = launch_mfma_update(J, k, grid, stream)) != 0) return e;
-            hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
+            hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs < kReduceGrid ? J.n_pairs : kReduceGrid), dim3(kStepThreads), 0,
+                               stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
         }
         return launch_finish<T>(J, stream);
@@ -1065,7 +1072,8 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
             hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
         }
-        hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs), dim3(kStepThreads), 0, stream, J, k);
+        hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs < kReduceGrid ? J.n_pairs : kReduceGrid), dim3(kStepThreads), 0,
+                               stream, J, k);
         if ((e = (int)hipGetLastError()) != 0) return e;
     }
     return launch_finish<T>(J, stream);
