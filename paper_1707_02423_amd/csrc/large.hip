@@ -348,6 +348,33 @@ __device__ inline T row_rest(const T* src, int nC, const GraphRef& Rg, int i, co
     return acc;
 }
 
+// Terms of row i that take the lane column's list entries past its first kLS
+// successors / kLP predecessors (only lanes with long lists loop).
+template <typename T>
+__device__ inline T col_rest(const T* src, int nC, const GraphRef& Rg, int i, const GraphRef& Cg, int sb, int ns,
+                             int pb, int np) {
+    T acc = T(0);
+    if (ns > kLS) {
+        const int e1 = uni(Rg.rp[i + 1]);
+        for (int e = uni(Rg.rp[i]); e < e1; ++e) {
+            const T* row = src + (long long)uni(Rg.ci[e]) * nC;
+            T in = T(0);
+            for (int q = kLS; q < ns; ++q) in = dev::fma_t(T(Cg.w[sb + q]), row[Cg.ci[sb + q]], in);
+            acc = dev::fma_t(T(Rg.w[e]), in, acc);
+        }
+    }
+    if (np > kLP) {
+        const int f1 = uni(Rg.cp[i + 1]);
+        for (int e = uni(Rg.cp[i]); e < f1; ++e) {
+            const T* row = src + (long long)uni(Rg.ri[e]) * nC;
+            T in = T(0);
+            for (int q = kLP; q < np; ++q) in = dev::fma_t(T(Cg.w[Cg.eid[pb + q]]), row[Cg.ri[pb + q]], in);
+            acc = dev::fma_t(T(Rg.w[uni(Rg.eid[e])]), in, acc);
+        }
+    }
+    return acc;
+}
+
 // ---------------------------------------------------------------- the operator
 // Launch k (1 .. max_iter): X_k = M_{Rg,Cg}(src) * sigma_{k-1} over the state
 // (nR x nC).  Plain pairs: src = Y_{k-1} (S_0 is the constant
@@ -355,7 +382,13 @@ __device__ inline T row_rest(const T* src, int nC, const GraphRef& Rg, int i, co
 // at odd k >= 3, those of S_{k-1} - S_{k-3}.  Resized pairs: src = V_{k-1},
 // X_k = U_k into slot k % 4; large_gram does the rest.  Launch max_iter + 1
 // computes only the last change of plain pairs.
-template <typename T>
+//
+// Two kernels share the tiles: large_step<T, false> every tile whose pair
+// gathers at k (plain pairs from k = 2, resized pairs from k = 1), and
+// large_step<T, true> the first update of plain pairs (from the constant S_0)
+// and the change-only launch.  Kept apart, the gather loop's register budget
+// is its own (four waves per SIMD instead of two).
+template <typename T, bool EDGE>
 __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
     __shared__ double red[2 * kNWStep];
     __shared__ NodeRec<T> trec[kTileRows];
@@ -369,6 +402,8 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         if (!uni(s->active)) continue;
         const bool rz = uni(s->rz) != 0;
         if (rz && !compute) continue;
+        const bool first = k == 1 && !rz;                 // S_0 is the constant
+        if ((compute && !first) == EDGE) continue;         // a tile of the other kernel
         const Tile tl = tile_at(J, t, s, p);
         const int nR = s->nR, nC = s->nC;
         const int j = tl.c0 + lane;
@@ -379,28 +414,20 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         const T c0v = T(1.0 / sqrt((double)s->nA * (double)s->nB));
         const T sig = T(1.0 / s->nu_k[(k - 1) & 3]);     // sigma_{k-1} (1 for S_0)
         const T sig3 = T(1.0 / s->nu_k[(k - 3) & 3]);    // sigma_{k-3}
-        const bool first = k == 1 && !rz;                 // S_0 is the constant
         const bool old_is_s0 = k == 3;
         // the lane column's neighbour lists in Cg (padding has zero weight)
-        const NodeRec<T>* rrec = recs_of<T>(J, p, 0);
         NodeRec<T> cr{};
         if (colv) cr = recs_of<T>(J, p, 1)[j];
         const int ns = cr.ns, np = cr.np;
-        const bool ovf = uni(dev::wave_max(max(ns - kLS, np - kLP))) > 0;
-        // CSR lists are read only by the first update and by long lists
-        GraphRef Rg{}, Cg{};
-        int sb = 0, pb = 0;
-        if (first || ovf) {
-            state_graphs(J, p, s, &Rg, &Cg);
-            sb = colv ? Cg.rp[j] : 0;
-            pb = colv ? Cg.cp[j] : 0;
-        }
         double nu2 = 0.0, d2 = 0.0;
         const int i0 = tl.r0 + wave * kRowsPerWave;
-        if (compute && !first && !ovf) {
+        if constexpr (!EDGE) {
+            // lanes whose column lists are longer than the slots
+            const bool ovf = uni(dev::wave_max(max(ns - kLS, np - kLP))) > 0;
             // the wave's row records, staged in LDS (rows past the end get
             // an empty record); then rows in groups of kUnroll, all of a
             // group's gathers issued before any is used
+            const NodeRec<T>* rrec = recs_of<T>(J, p, 0);
             if (lane < kRowsPerWave) {
                 NodeRec<T> r{};
                 if (i0 + lane < nR) r = rrec[i0 + lane];
@@ -434,114 +461,62 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
                     const T v = acc[u] * sig;
                     if (i < nR && colv) {
                         dst[(long long)i * nC + j] = v;
+                        if (!ovf) nu2 += (double)v * (double)v;
+                    }
+                }
+            }
+            if (ovf) {
+                // the terms of the long lists' later entries, added to the
+                // entries this lane has just written (no other lane writes them)
+                GraphRef Rg, Cg;
+                state_graphs(J, p, s, &Rg, &Cg);
+                const int sb = colv ? Cg.rp[j] : 0, pb = colv ? Cg.cp[j] : 0;
+                for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                    const int i = i0 + rr;
+                    if (i >= nR) break;
+                    const T add = col_rest<T>(src, nC, Rg, i, Cg, sb, ns, pb, np);
+                    if (colv) {
+                        const long long o = (long long)i * nC + j;
+                        const T v = dst[o] + add * sig;
+                        dst[o] = v;
                         nu2 += (double)v * (double)v;
                     }
                 }
             }
-            if (!rz && want_delta) {
-                for (int rr = 0; rr < kRowsPerWave; ++rr) {
-                    const int i = i0 + rr;
-                    if (i >= nR) break;
-                    if (colv) {
-                        const long long o = (long long)i * nC + j;
-                        const T a = T(src[o] * sig);
-                        const T b = old_is_s0 ? c0v : T(old[o] * sig3);
-                        const double d = (double)a - (double)b;
-                        d2 += d * d;
-                    }
-                }
+        } else if (compute) {
+            // the first update: Y_1[i][j] = c0 (outw_Rg(i) outw_Cg(j) + inw_Rg(i) inw_Cg(j))
+            GraphRef Rg, Cg;
+            state_graphs(J, p, s, &Rg, &Cg);
+            T ra = T(0), qa = T(0);
+            if (colv) {
+                const int sb = Cg.rp[j], pb = Cg.cp[j];
+                for (int e = 0; e < ns; ++e) ra += T(Cg.w[sb + e]);
+                for (int e = 0; e < np; ++e) qa += T(Cg.w[Cg.eid[pb + e]]);
             }
-            if (rz) continue;
-            tile_partials(J, t, nu2, d2, red);
-            continue;
-        }
-        NodeRec<T> nxt = rrec[min(i0, nR - 1)];
-        for (int rr = 0; rr < kRowsPerWave; ++rr) {
-            const int i = i0 + rr;
-            if (i >= nR) break;
-            const NodeRec<T> rw = nxt;
-            nxt = rrec[min(i + 1, nR - 1)];  // prefetch the wave's next row
-            if (compute) {
-                T acc = T(0);
-                const int nsR = uni(rw.ns), npR = uni(rw.np);
-                if (!first && !ovf && nsR <= kLS && npR <= kLP) {
-                    int ru[kLS], qu[kLP];
-                    T rwt[kLS], qwt[kLP];
-#pragma unroll
-                    for (int a = 0; a < kLS; ++a) {
-                        ru[a] = uni(rw.su[a]);
-                        rwt[a] = uni(rw.sw[a]);
-                    }
-#pragma unroll
-                    for (int b = 0; b < kLP; ++b) {
-                        qu[b] = uni(rw.pu[b]);
-                        qwt[b] = uni(rw.pw[b]);
-                    }
-                    switch (nsR * 4 + npR) {
-                        case 0: break;
-                        case 1: acc = row_terms<T, 0, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 2: acc = row_terms<T, 0, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 3: acc = row_terms<T, 0, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 4: acc = row_terms<T, 1, 0>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 5: acc = row_terms<T, 1, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 6: acc = row_terms<T, 1, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 7: acc = row_terms<T, 1, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 8: acc = row_terms<T, 2, 0>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 9: acc = row_terms<T, 2, 1>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        case 10: acc = row_terms<T, 2, 2>(src, nC, ru, rwt, qu, qwt, cr); break;
-                        default: acc = row_terms<T, 2, 3>(src, nC, ru, rwt, qu, qwt, cr); break;
-                    }
-                    acc *= sig;
-                } else if (first) {
-                    // S_0 constant: Y_1[i][j] = c0 (outw_Rg(i) outw_Cg(j) + inw_Rg(i) inw_Cg(j))
-                    T ra = T(0), rb = T(0), qa = T(0), qb = T(0);
-                    if (colv) {
-                        for (int e = 0; e < ns; ++e) ra += T(Cg.w[sb + e]);
-                        for (int e = 0; e < np; ++e) qa += T(Cg.w[Cg.eid[pb + e]]);
-                    }
-                    for (int e = Rg.rp[i]; e < Rg.rp[i + 1]; ++e) rb += T(Rg.w[e]);
-                    for (int e = Rg.cp[i]; e < Rg.cp[i + 1]; ++e) qb += T(Rg.w[Rg.eid[e]]);
-                    acc = c0v * (rb * ra + qb * qa);
-                } else {
-                    if (!ovf) state_graphs(J, p, s, &Rg, &Cg);  // a row with long lists
-                    const int e1 = uni(Rg.rp[i + 1]);
-                    for (int e = uni(Rg.rp[i]); e < e1; ++e) {
-                        const int u = uni(Rg.ci[e]);
-                        const T wu = T(Rg.w[e]);
-                        const T* row = src + (long long)u * nC;
-                        T in = T(0);
-#pragma unroll
-                        for (int q = 0; q < kLS; ++q) in = dev::fma_t(cr.sw[q], row[cr.su[q]], in);
-                        if (ovf)
-                            for (int q = kLS; q < ns; ++q) in = dev::fma_t(T(Cg.w[sb + q]), row[Cg.ci[sb + q]], in);
-                        acc = dev::fma_t(wu, in, acc);
-                    }
-                    const int f1 = uni(Rg.cp[i + 1]);
-                    for (int e = uni(Rg.cp[i]); e < f1; ++e) {
-                        const int u = uni(Rg.ri[e]);
-                        const T wu = T(Rg.w[uni(Rg.eid[e])]);
-                        const T* row = src + (long long)u * nC;
-                        T in = T(0);
-#pragma unroll
-                        for (int q = 0; q < kLP; ++q) in = dev::fma_t(cr.pw[q], row[cr.pu[q]], in);
-                        if (ovf)
-                            for (int q = kLP; q < np; ++q)
-                                in = dev::fma_t(T(Cg.w[Cg.eid[pb + q]]), row[Cg.ri[pb + q]], in);
-                        acc = dev::fma_t(wu, in, acc);
-                    }
-                    acc *= sig;
-                }
+            for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                const int i = i0 + rr;
+                if (i >= nR) break;
+                T rb = T(0), qb = T(0);
+                for (int e = Rg.rp[i]; e < Rg.rp[i + 1]; ++e) rb += T(Rg.w[e]);
+                for (int e = Rg.cp[i]; e < Rg.cp[i + 1]; ++e) qb += T(Rg.w[Rg.eid[e]]);
+                const T acc = c0v * (rb * ra + qb * qa);
                 if (colv) {
                     dst[(long long)i * nC + j] = acc;
                     nu2 += (double)acc * (double)acc;
                 }
             }
-            if (!rz && want_delta && colv) {
-                const long long o = (long long)i * nC + j;
-                const T a = T(src[o] * sig);                        // S_{k-1}
-                const T b = old_is_s0 ? c0v : T(old[o] * sig3);     // S_{k-3}
-                const double d = (double)a - (double)b;
-                d2 += d * d;
+        }
+        if (!rz && want_delta) {
+            for (int rr = 0; rr < kRowsPerWave; ++rr) {
+                const int i = i0 + rr;
+                if (i >= nR) break;
+                if (colv) {
+                    const long long o = (long long)i * nC + j;
+                    const T a = T(src[o] * sig);                        // S_{k-1}
+                    const T b = old_is_s0 ? c0v : T(old[o] * sig3);     // S_{k-3}
+                    const double d = (double)a - (double)b;
+                    d2 += d * d;
+                }
             }
         }
         if (rz) continue;   // norms of resized pairs come from large_gram
@@ -1066,8 +1041,15 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
         if ((e = (int)hipGetLastError()) != 0) return e;
     }
     for (int k = 1; k <= J.max_iter + 1; ++k) {
-        hipLaunchKernelGGL(large_step<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
-        if ((e = (int)hipGetLastError()) != 0) return e;
+        // each kernel skips the tiles of the other (see large_step)
+        if (k == 1 || k == J.max_iter + 1) {
+            hipLaunchKernelGGL((large_step<T, true>), dim3(grid), dim3(kStepThreads), 0, stream, J, k);
+            if ((e = (int)hipGetLastError()) != 0) return e;
+        }
+        if (k <= J.max_iter && (k >= 2 || J.resize)) {
+            hipLaunchKernelGGL((large_step<T, false>), dim3(grid), dim3(kStepThreads), 0, stream, J, k);
+            if ((e = (int)hipGetLastError()) != 0) return e;
+        }
         if (J.resize) {
             hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
