@@ -1026,10 +1026,21 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
     if ((e = (int)hipGetLastError()) != 0) return e;
     hipLaunchKernelGGL(large_tile_map, dim3(J.n_pairs < 4096 ? J.n_pairs : 4096), dim3(256), 0, stream, J);
     if ((e = (int)hipGetLastError()) != 0) return e;
+    // the tile kernels (gathers, matrix-core stages): up to one workgroup
+    // per tile, dispatched in tile order (the hardware's dispatch balances
+    // tiles of unequal cost better than a grid-stride loop: 1.19 against
+    // 1.48 ms per gather launch on 64 pairs of 512-2048 nodes), at most 8x
+    // the base grid; a call whose pairs mostly ran elsewhere (a pair filter
+    // is set) keeps the base grid, so that its empty launches stay cheap.
+    // A multiple of 8 keeps the XCD split of tile_range.
+    long long gg = J.filter ? (long long)grid : (long long)J.n_pairs * large_tiles(J.max_nodes);
+    gg = gg < 8ll * grid ? gg : 8ll * grid;
+    gg = (gg + 7) / 8 * 8;
+    const int ggrid = (int)(gg > grid ? gg : grid);
     if (J.mfma) {  // BF16 matrix-core products (plain FP32 pairs)
         if ((e = launch_mfma_prep(J, stream)) != 0) return e;
         for (int k = 1; k <= J.max_iter + 1; ++k) {
-            if ((e = launch_mfma_update(J, k, grid, stream)) != 0) return e;
+            if ((e = launch_mfma_update(J, k, ggrid, stream)) != 0) return e;
             hipLaunchKernelGGL(large_reduce, dim3(J.n_pairs < kReduceGrid ? J.n_pairs : kReduceGrid), dim3(kStepThreads), 0,
                                stream, J, k);
             if ((e = (int)hipGetLastError()) != 0) return e;
@@ -1040,17 +1051,6 @@ static int launch_large_t(const LargeJob& J, int grid, hipStream_t stream) {
         hipLaunchKernelGGL(large_gram<T>, dim3(grid), dim3(kStepThreads), 0, stream, J, 0);
         if ((e = (int)hipGetLastError()) != 0) return e;
     }
-    // the gather kernel: up to one workgroup per tile, dispatched in tile
-    // order (the hardware's dispatch balances tiles of unequal cost better
-    // than a grid-stride loop: 1.19 against 1.48 ms per launch on 64 pairs
-    // of 512-2048 nodes), at most 8x the base grid; a call whose pairs
-    // mostly ran elsewhere (a pair filter is set) keeps the base grid, so
-    // that its empty launches stay cheap.  A multiple of 8 keeps the XCD
-    // split of tile_range.
-    long long gg = J.filter ? (long long)grid : (long long)J.n_pairs * large_tiles(J.max_nodes);
-    gg = gg < 8ll * grid ? gg : 8ll * grid;
-    gg = (gg + 7) / 8 * 8;
-    const int ggrid = (int)(gg > grid ? gg : grid);
     for (int k = 1; k <= J.max_iter + 1; ++k) {
         // each kernel skips the tiles of the other (see large_step)
         if (k == 1 || k == J.max_iter + 1) {
