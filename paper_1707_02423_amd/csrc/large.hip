@@ -1009,7 +1009,7 @@ static int launch_finish(const LargeJob& J, hipStream_t stream) {
     hipLaunchKernelGGL(large_final<T>, dim3(tiles < 64 ? tiles : 64, J.n_pairs), dim3(kFinalThreads), 0, stream, J);
     int e = (int)hipGetLastError();
     if (e != 0) return e;
-    hipLaunchKernelGGL(large_sort_lines<T>, dim3(groups < 64 ? groups : 64, J.n_pairs), dim3(kSortThreads),
+    hipLaunchKernelGGL(large_sort_lines<T>, dim3(groups < 512 ? groups : 512, J.n_pairs), dim3(kSortThreads),
                        large_sort_lds(J.max_nodes, (int)sizeof(T)), stream, J);
     if ((e = (int)hipGetLastError()) != 0) return e;
     hipLaunchKernelGGL(large_finish<T>, dim3(J.n_pairs), dim3(kFinishThreads), large_finish_lds(J.max_nodes), stream,
