@@ -41,7 +41,12 @@ using dev::better;
 using dev::uni;
 using dev::wave_sum;
 
-constexpr int kUnroll = 4;                      // rows whose gathers are in flight together
+// rows whose gathers are in flight together (FP64: two, which keeps the
+// gather kernel at four waves per SIMD)
+template <typename T>
+constexpr int unroll_of() {
+    return sizeof(T) == 8 ? 2 : 4;
+}
 constexpr int kReduceGrid = 2048;               // workgroups of the per-pair reduction
 constexpr int kFinishThreads = 1024;
 constexpr int kLS = 2;                          // successors per lane column in registers
@@ -421,6 +426,7 @@ __global__ __launch_bounds__(kStepThreads) void large_step(LargeJob J, int k) {
         const int ns = cr.ns, np = cr.np;
         double nu2 = 0.0, d2 = 0.0;
         const int i0 = tl.r0 + wave * kRowsPerWave;
+        constexpr int kUnroll = unroll_of<T>();
         if constexpr (!EDGE) {
             // lanes whose column lists are longer than the slots
             const bool ovf = uni(dev::wave_max(max(ns - kLS, np - kLP))) > 0;
